@@ -1,0 +1,119 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module holds none of the transforms' arithmetic: it only draws cubes with
+numpy's PCG64 generator. The shapes and value distributions stand in for the
+paper's workloads (a voxelized depth scene with planes, Sec. 6.2; a ray buried
+in noise, Sec. 4.1; corner voxels and the centre of a cube, Sec. 5.1), whose data
+are not available. Planes and segments are drawn as rounded continuous planes
+and lines, not as the transforms' own digital sets.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "uniform_int_cube", "normal_cube", "point_cloud_with_planes",
+    "noise_with_segments", "mixed_batch", "corners_and_centre", "WORKLOADS",
+]
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def uniform_int_cube(N: int, lo: int = 0, hi: int = 255, seed: int = 1) -> np.ndarray:
+    """int32 cube, values uniform integers in [lo, hi]."""
+    return _rng(seed).integers(lo, hi + 1, size=(N, N, N), dtype=np.int64).astype(np.int32)
+
+
+def normal_cube(N: int, seed: int = 5) -> np.ndarray:
+    """float32 cube, values N(0,1)."""
+    return _rng(seed).standard_normal(size=(N, N, N)).astype(np.float32)
+
+
+def _random_plane_voxels(N: int, rng: np.random.Generator):
+    """Voxels of a rounded continuous plane with a random normal (upper
+    hemisphere) through a random point of the cube."""
+    n = rng.standard_normal(3)
+    n /= np.linalg.norm(n)
+    if n[2] < 0:
+        n = -n
+    p0 = rng.uniform(0, N - 1, size=3)
+    c = int(np.argmax(np.abs(n)))
+    a, b = [i for i in range(3) if i != c]
+    ia, ib = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+    ic = np.rint(p0[c] - (n[a] * (ia - p0[a]) + n[b] * (ib - p0[b])) / n[c]).astype(np.int64)
+    ok = (ic >= 0) & (ic < N)
+    coords = np.zeros((3, int(ok.sum())), dtype=np.int64)
+    coords[a], coords[b], coords[c] = ia[ok], ib[ok], ic[ok]
+    return coords
+
+
+def point_cloud_with_planes(N: int = 512, occupancy: float = 0.01, n_planes: int = 8,
+                            plane_value: int = 16, seed: int = 2) -> np.ndarray:
+    """int32 cube: a sparse point cloud (value 1) at the given occupancy, chosen
+    uniformly without replacement, plus planes with random normals inside the
+    hemisphere and random offsets (value ``plane_value``, overwriting)."""
+    rng = _rng(seed)
+    vol = np.zeros(N * N * N, dtype=np.int32)
+    count = int(round(occupancy * N ** 3))
+    idx = rng.choice(N ** 3, size=count, replace=False)
+    vol[idx] = 1
+    vol = vol.reshape(N, N, N)
+    for _ in range(n_planes):
+        x, y, z = _random_plane_voxels(N, rng)
+        vol[x, y, z] = plane_value
+    return vol
+
+
+def noise_with_segments(N: int = 128, n_segments: int = 64, seg_value: int = 8,
+                        noise_max: int = 3, seed: int = 3) -> np.ndarray:
+    """int32 cube: uniform integer noise in [0, noise_max] plus random 3D digital
+    segments (rounded continuous lines of length >= N/4 along their dominant
+    axis) that add ``seg_value`` to every voxel they visit."""
+    rng = _rng(seed)
+    vol = rng.integers(0, noise_max + 1, size=(N, N, N), dtype=np.int64).astype(np.int32)
+    for _ in range(n_segments):
+        d = rng.standard_normal(3)
+        d /= np.max(np.abs(d))              # unit step along the dominant axis
+        length = int(rng.integers(max(1, N // 4), N + 1))
+        p0 = rng.uniform(0, N - 1, size=3)
+        t = np.arange(length)[:, None]
+        pts = np.rint(p0[None, :] + t * d[None, :]).astype(np.int64)
+        ok = np.all((pts >= 0) & (pts < N), axis=1)
+        pts = pts[ok]
+        if len(pts):
+            np.add.at(vol, (pts[:, 0], pts[:, 1], pts[:, 2]), seg_value)
+    return vol
+
+
+def mixed_batch(counts=((32, 48), (64, 32), (128, 12), (256, 4)), seed0: int = 1000):
+    """List of float32 N(0,1) cubes of mixed sizes; cube i uses seed seed0 + i."""
+    cubes, i = [], 0
+    for N, c in counts:
+        for _ in range(c):
+            cubes.append(normal_cube(N, seed=seed0 + i))
+            i += 1
+    return cubes
+
+
+def corners_and_centre(N: int = 64, value: int = 1) -> np.ndarray:
+    """int32 cube with the 8 corner voxels and the centre voxel set (Sec. 5.1)."""
+    vol = np.zeros((N, N, N), dtype=np.int32)
+    for x in (0, N - 1):
+        for y in (0, N - 1):
+            for z in (0, N - 1):
+                vol[x, y, z] = value
+    vol[N // 2, N // 2, N // 2] = value
+    return vol
+
+
+# Named workloads with the sizes they are quoted at.
+WORKLOADS = {
+    "drt_n32_uniform": dict(kind="drt", N=32, dtype="int32",
+                            make=lambda: uniform_int_cube(32, 0, 255, seed=1)),
+    "drt_n512_pointcloud_planes": dict(kind="drt", N=512, dtype="int32",
+                                       make=lambda: point_cloud_with_planes(512, seed=2)),
+    "djt_n128_segments": dict(kind="djt", N=128, dtype="int32",
+                              make=lambda: noise_with_segments(128, seed=3)),
+}
