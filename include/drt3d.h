@@ -1,0 +1,166 @@
+/*
+ * drt3d.h — C ABI of the MI355X (gfx950) library for the 3D multiscale discrete
+ * Radon transform of planes (DRT), the 3D discrete John transform of lines (DJT)
+ * and the DRT adjoint, after Marichal-Hernandez et al., "Three-dimensional
+ * multiscale discrete Radon and John transforms" (arXiv 2501.13664).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Volume: N x N x N, N = 2^n with 2 <= N <= DRT3D_MAX_N, C order [x][y][z]
+ *   (z fastest), device memory owned by the caller. Inputs are never modified.
+ * Dodecants: bit k of `mask` (k = 0..11) selects dodecant k, the input seen
+ *   through row k of the InOrder table of Algorithm 2 (Sec. 3.2), read as:
+ *   mirror every original axis |o_j| with o_j < 0, then send original axis i to
+ *   primed axis |o_i|. Under this reading the 12 frames tile the hemisphere of
+ *   plane normals (Sec. 3.2) and of line directions (Sec. 4.1). Outputs hold the
+ *   selected dodecants in increasing k. DRT3D_ALL selects all twelve.
+ * DRT output (Sec. 3.1, eq. (9)): [popcount(mask)][N][N][3N-2], element
+ *   [j][s1][s2][dd] = sum over x',y' of g_k(x', y', l_{s1}(x') + l_{s2}(y') + N-1-dd),
+ *   with l the discrete line of eq. (4) and g_k the frame-k view of the volume;
+ *   dd = N-1-d mirrors the displacement d of eq. (9), so the non-null values of
+ *   slope pair (s1,s2) occupy dd = 0..N-1+s1+s2 (Sec. 3.2). Zero tails are written.
+ * DJT output (Sec. 4.1, eq. (13)): [popcount(mask)][N][N][2N-1][2N-1], element
+ *   [j][s1][s2][e1][e2] = sum over u of g_k(l_{s1}(u)+N-1-e1, l_{s2}(u)+N-1-e2, u):
+ *   lines driven along z' with slopes (s1,s2) over (x',y'); e = N-1-d.
+ * Adjoint (Sec. 5.1, eq. (16)-(17)): vol_out[x][y][z] = sum over the selected
+ *   dodecants and all slope pairs of the DRT value of the one plane through the
+ *   voxel; the exact transpose of drt3d_forward (no normalisation).
+ * Arithmetic: DRT3D_I32 is int32 with two's-complement wrap (results are exact
+ *   modulo 2^32, bit-identical to any exact summation order); DRT3D_F32 is
+ *   float32 accumulation in the paper's recursion order.
+ * Workspace: device memory of at least the size returned by the matching
+ *   *_workspace_bytes query, owned by the caller, 256-byte aligned; its contents
+ *   need not be initialised and are clobbered. Calls that share a workspace must
+ *   not overlap in time.
+ * Streams: every call is stream-ordered and asynchronous on `stream` (a
+ *   hipStream_t; NULL = the default stream). Errors in argument validation are
+ *   reported before any GPU work is queued.
+ * Errors: functions return DRT3D_OK (0) or a negative status; the message of the
+ *   last failure on the calling thread is available from drt3d_last_error().
+ *   No C++ exception crosses this interface.
+ * Alignment: vol/out/proj/workspace pointers must be 16-byte aligned.
+ */
+#ifndef DRT3D_H
+#define DRT3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DRT3D_ABI_VERSION 1
+#define DRT3D_MAX_N 1024
+#define DRT3D_ALL 0xFFFu
+
+typedef enum {
+    DRT3D_I32 = 0, /* int32 in, int32 out, wrap-around arithmetic */
+    DRT3D_F32 = 1  /* float32 in, float32 out */
+} drt3d_dtype;
+
+typedef enum {
+    DRT3D_OK = 0,
+    DRT3D_EINVAL = -1,      /* bad argument: N, mask, null or misaligned pointer, dtype, count */
+    DRT3D_ENOMEM = -2,      /* workspace smaller than the query, or a host allocation failed */
+    DRT3D_EHIP = -3,        /* a HIP runtime call failed (message names it) */
+    DRT3D_EUNSUPPORTED = -4 /* no gfx950 device, or a feature not built */
+} drt3d_status;
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* drt3d_last_error(void);
+int drt3d_abi_version(void);
+
+/* ---- size queries (host only, pure) ------------------------------------ */
+/* Elements of the DRT output: popcount(mask) * N * N * (3N-2); 0 if invalid. */
+size_t drt3d_out_elems(int N, uint32_t mask);
+/* Elements of the DJT output: popcount(mask) * N * N * (2N-1)^2; 0 if invalid. */
+size_t djt3d_out_elems(int N, uint32_t mask);
+/* Workspace bytes for drt3d_forward / djt3d_forward / drt3d_adjoint (any tuning
+ * choice fits). 0 if the arguments are invalid. */
+size_t drt3d_workspace_bytes(int N, uint32_t mask, int dtype);
+size_t djt3d_workspace_bytes(int N, uint32_t mask, int dtype);
+size_t drt3d_adjoint_workspace_bytes(int N, uint32_t mask, int dtype);
+/* Workspace bytes for the batched variants over `count` volumes of sizes Ns[]. */
+size_t drt3d_forward_batched_workspace_bytes(int count, const int* Ns, uint32_t mask, int dtype);
+size_t djt3d_forward_batched_workspace_bytes(int count, const int* Ns, uint32_t mask, int dtype);
+size_t drt3d_adjoint_batched_workspace_bytes(int count, const int* Ns, uint32_t mask, int dtype);
+
+/* ---- transforms ----------------------------------------------------------- */
+/* 3D DRT of planes, Algorithm 1 (stage map eq. (11)) over the dodecants of
+ * `mask` (Algorithm 2's input frames). vol: [N][N][N] of dtype; out:
+ * drt3d_out_elems(N, mask) elements of dtype, fully overwritten. */
+int drt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype,
+                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* 3D DJT of lines, Algorithm 3 (stage map eq. (15)), driving axis z', over the
+ * dodecants of `mask`. out: djt3d_out_elems(N, mask) elements, overwritten. */
+int djt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype,
+                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* DRT adjoint (backprojection), Algorithm 1 reversed with eq. (17) (Sec. 5.1),
+ * summed over the dodecants of `mask`. proj: the drt3d_forward layout for the
+ * same (N, mask); vol_out: [N][N][N], overwritten. */
+int drt3d_adjoint(const void* proj, void* vol_out, int N, uint32_t mask, int dtype,
+                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---- batched variants ----------------------------------------------------- */
+/* `count` independent transforms of possibly different N in one set of
+ * persistent launches (one per pass slot), replayed from a cached hipGraph
+ * when the same shapes, mask, dtype and workspace recur. vols/outs (device
+ * pointers) and Ns live in host memory; every volume uses the same mask and
+ * dtype. Results are bit-identical to the single-volume calls. */
+int drt3d_forward_batched(int count, const void* const* vols, void* const* outs,
+                          const int* Ns, uint32_t mask, int dtype,
+                          void* workspace, size_t workspace_bytes, void* stream);
+int djt3d_forward_batched(int count, const void* const* vols, void* const* outs,
+                          const int* Ns, uint32_t mask, int dtype,
+                          void* workspace, size_t workspace_bytes, void* stream);
+int drt3d_adjoint_batched(int count, const void* const* projs, void* const* vols_out,
+                          const int* Ns, uint32_t mask, int dtype,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---- tuning ----------------------------------------------------------------- */
+/* Pick the stage grouping (stages fused per pass), tile width and LDS budget
+ * for size class N and dtype by timing every candidate on the GPU with the given
+ * buffers (vol: N^3, out: drt3d_out_elems(N, DRT3D_ALL), workspace of
+ * drt3d_workspace_bytes(N, DRT3D_ALL, dtype)); `out` is clobbered. The choice is
+ * kept for the process and, if the environment variable DRT3D_TUNE_CACHE names
+ * a file, appended there. Every candidate computes bit-identical results. */
+int drt3d_autotune(int N, int dtype, const void* vol, void* out,
+                   void* workspace, size_t workspace_bytes, void* stream);
+/* Current tuning choice of size class N as text (for logs and tests). */
+const char* drt3d_tuning_string(int N, int dtype);
+/* Force a tuning choice from its text form (as printed by drt3d_tuning_string);
+ * used by determinism tests. */
+int drt3d_set_tuning(int N, int dtype, const char* text);
+
+/* ---- profiling -------------------------------------------------------------- */
+/* When enabled (nonzero), each pass launch of the calls that follow records a
+ * HIP event pair on the call's stream; drt3d_pass_times reports, per kernel
+ * name (e.g. "drt_fwd_y2"), the summed milliseconds, the launch count and the
+ * algorithmic bytes (reads of each pass's input extent plus writes of its
+ * output extent) since the last reset. Synchronises the recorded events. */
+int drt3d_profile_enable(int on);
+int drt3d_profile_reset(void);
+/* Writes up to `cap` records; returns the number of distinct kernel names. */
+int drt3d_pass_times(char* names /* cap x 32 chars */, double* ms, long long* launches,
+                     double* bytes, int cap);
+
+/* ---- introspection (host only, no GPU work) --------------------------------- */
+/* Frame view of dodecant k (0..11) at size N as an affine element offset
+ * out = {base, sx, sy, sd, group}:
+ *   kind 0 (DRT):  g_k(x', y', N-1-dd) = V_group[base + sx*x' + sy*y' + sd*dd],
+ *                  V_0 = [x][y][z] (the volume), V_1 = [x][z][y], V_2 = [y][z][x];
+ *   kind 1 (DJT):  g_k(N-1-e1, N-1-e2, v) = vol[base + sx*e1 + sy*e2 + sd*v].  */
+int drt3d_frame_map(int k, int N, int kind, int out[5]);
+/* Text description of the launches one call would make (op 0: drt3d_forward,
+ * 1: drt3d_adjoint, 2: djt3d_forward), one line per launch:
+ * "name kind=<k> wg=<work groups> block=<threads> lds=<bytes> bytes=<algorithmic>".
+ * Returns the number of launches, or a negative status. */
+int drt3d_plan_text(int op, int N, uint32_t mask, int dtype, char* buf, size_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DRT3D_H */

@@ -1,0 +1,69 @@
+// Internal declarations shared by the device code and the host runtime of the
+// drt3d library. Not part of the public interface (include/drt3d.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace drt3d {
+
+// Affine element offset of a frame view of an N^3 volume:
+//   offset = base + sx * a + sy * b + sd * c,
+// with (a, b) the two in-plane primed coordinates and c the third one (the
+// displacement for the DRT, the driving coordinate for the DJT).
+// N <= 1024 keeps every term inside int32.
+struct FrameMap {
+    int base, sx, sy, sd;
+    int group;  // volume layout the map addresses (DRT: 0 z-, 1 y-, 2 x-normal)
+};
+
+constexpr int kMaxSlots = 12;
+
+// One DRT pass: K consecutive stages m0..m0+K-1 of eq. (11) restricted to one
+// axis (x: slope s1, or y: slope s2), for every column group of every
+// dodecant slot, forward or adjoint (eq. (17)). Work items are
+// (slot, group, tile) flattened; `wg_begin` is the first flattened index of
+// this descriptor inside its launch.
+struct DrtDesc {
+    long long wg_begin;
+    long long src_slot_stride, dst_slot_stride;  // elements between slots
+    const void* src;                             // stage buffer (src_mode 0)
+    void* dst;                                   // stage buffer (dst_mode 0)
+    const void* vsrc[3];                         // volume layouts (src_mode 1)
+    void* vdst[3];                               // volume accumulators (dst_mode 1)
+    int groups, ntiles, nslots;
+    int N, n, axis, m0, K;
+    int E_in, P_in, E_out, P_out;
+    int T, H, L, Lp;
+    int src_mode, dst_mode, adjoint;
+    int phys[kMaxSlots];   // slot -> slot index inside the src/dst stage buffers
+    int accum[kMaxSlots];  // dst_mode 1: add into the volume (1) or overwrite (0)
+    FrameMap fm[kMaxSlots];
+};
+
+// One DJT stage m -> m+1 of eq. (15) for every (block pair, slope pair) group
+// of every dodecant slot. Work items are (slot, group, row band) flattened.
+struct DjtDesc {
+    long long wg_begin;
+    long long src_slot_stride, dst_slot_stride;
+    const void* src;  // stage buffer, or the volume when src_mode == 1
+    void* dst;
+    int groups, nbands, rows_per_band, nslots;
+    int N, n, m;
+    int E_in, E_out;  // square plane extents (row pitch == extent)
+    int src_mode;
+    int final_stage;  // output is the caller's buffer: stream past the caches
+    FrameMap fm[kMaxSlots];
+};
+
+// Launchers (device code translation unit).
+hipError_t launch_drt_pass(int is_float, const DrtDesc* d_descs, int ndesc, long long total_wg,
+                           int block, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t launch_djt_stage(int is_float, const DjtDesc* d_descs, int ndesc, long long total_wg,
+                            int block, int grid, hipStream_t s);
+// out[b][c][r] (+)= in[b][r][c], for b < batches, r < R, c < C.
+hipError_t launch_transpose(int is_float, const void* in, void* out, int R, int C, int batches,
+                            int add, hipStream_t s);
+hipError_t set_drt_lds_limit(int is_float, size_t bytes);
+
+}  // namespace drt3d

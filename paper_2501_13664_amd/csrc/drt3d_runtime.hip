@@ -1,0 +1,1328 @@
+// Host runtime and C ABI of the drt3d library (see include/drt3d.h).
+//
+// Every call becomes an ordered list of steps; a step is one kernel launch
+// (a DRT pass, a DJT stage or a transpose) described by its descriptors. A
+// step carries a canonical key; the batched entry points merge the steps of
+// all volumes that share a key into a single persistent launch, in key order,
+// which preserves each volume's own order.
+//
+// DRT forward of one cube: transposes that make the y- and x-normal frames'
+// displacement axis contiguous, then the x-passes (stages of slope s1) and
+// the y-passes (slope s2), each fusing K stages of eq. (11) in LDS. The
+// adjoint runs the mirrored passes in reverse (eq. (17)); its last pass adds
+// every dodecant into one accumulator per frame group, and the accumulators
+// of the y- and x-normal groups are transposed back into the caller's volume.
+// The DJT runs one launch per stage of eq. (15).
+//
+// Single-volume calls process the dodecants in chunks that keep the stage
+// buffers under a fixed budget; batched calls keep every dodecant in flight.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/drt3d.h"
+#include "drt3d_internal.h"
+
+namespace drt3d {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return fail(DRT3D_EHIP, "%s failed: %s (%d)", #expr, hipGetErrorString(e_), (int)e_);     \
+    } while (0)
+
+#define TRY(expr)                  \
+    do {                           \
+        int rc_ = (expr);          \
+        if (rc_ != DRT3D_OK) return rc_; \
+    } while (0)
+
+static int ilog2_exact(int N)
+{
+    if (N < 2 || N > DRT3D_MAX_N) return -1;
+    int n = 0;
+    while ((1 << n) < N) ++n;
+    return (1 << n) == N ? n : -1;
+}
+
+static int popcount12(uint32_t mask)
+{
+    int c = 0;
+    for (int k = 0; k < 12; ++k) c += (mask >> k) & 1u;
+    return c;
+}
+
+static inline long long round4(long long x) { return (x + 3) & ~3LL; }
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------------ frames
+// Row k of Algorithm 2's InOrder table (1-based signed axis numbers).
+static const int kInOrder[12][3] = {
+    {1, 2, 3},   {-2, 1, 3},   {-1, -2, 3},  {2, -1, 3}, {-1, -3, -2}, {-3, -1, 2},
+    {3, -1, -2}, {1, 3, -2},   {-3, -2, -1}, {-2, -3, 1}, {-2, 3, -1}, {3, 2, -1},
+};
+
+// Reading of a row: original axis i is mirrored iff some entry o_j < 0 has
+// |o_j| = i+1, and original axis i carries primed axis |o_i|-1.
+struct AxisMap {
+    int primed;  // 0: x', 1: y', 2: z'
+    int mirror;
+};
+
+static void frame_axes(int k, AxisMap out[3])
+{
+    for (int i = 0; i < 3; ++i) {
+        const int o = kInOrder[k][i];
+        out[i].primed = (o < 0 ? -o : o) - 1;
+        out[i].mirror = 0;
+    }
+    for (int j = 0; j < 3; ++j)
+        if (kInOrder[k][j] < 0) out[-kInOrder[k][j] - 1].mirror = 1;
+}
+
+// DRT frame group of dodecant k: 0 if z' is along z, 1 along y, 2 along x.
+static int drt_group(int k)
+{
+    AxisMap a[3];
+    frame_axes(k, a);
+    for (int i = 0; i < 3; ++i)
+        if (a[i].primed == 2) return i == 2 ? 0 : (i == 1 ? 1 : 2);
+    return 0;
+}
+
+// Layout V_g[A][B][C] of group g's copy of the volume, C contiguous:
+//   g0: [x][y][z] (the caller's volume), g1: [x][z][y], g2: [y][z][x].
+static void group_layout(int g, int axes[3])
+{
+    if (g == 0) { axes[0] = 0; axes[1] = 1; axes[2] = 2; }
+    else if (g == 1) { axes[0] = 0; axes[1] = 2; axes[2] = 1; }
+    else { axes[0] = 1; axes[1] = 2; axes[2] = 0; }
+}
+
+// g_k(x', y', N-1-dd) = V_g[base + sx x' + sy y' + sd dd].
+static FrameMap drt_frame_map(int k, int N)
+{
+    AxisMap ax[3];
+    frame_axes(k, ax);
+    FrameMap f{};
+    f.group = drt_group(k);
+    int axes[3];
+    group_layout(f.group, axes);
+    const long long mult[3] = {(long long)N * N, N, 1};
+    long long base = 0, sx = 0, sy = 0, sd = 0;
+    for (int r = 0; r < 3; ++r) {
+        const AxisMap& m = ax[axes[r]];
+        const long long M = mult[r];
+        const long long beta = m.mirror ? -1 : 1;
+        if (m.mirror) base += M * (N - 1);
+        if (m.primed == 0) sx += M * beta;
+        else if (m.primed == 1) sy += M * beta;
+        else { base += M * beta * (N - 1); sd -= M * beta; }  // z' = N-1-dd
+    }
+    f.base = (int)base; f.sx = (int)sx; f.sy = (int)sy; f.sd = (int)sd;
+    return f;
+}
+
+// DJT stage 0: g_k(N-1-e1, N-1-e2, v) = vol[base + sx e1 + sy e2 + sd v].
+static FrameMap djt_frame_map(int k, int N)
+{
+    AxisMap ax[3];
+    frame_axes(k, ax);
+    FrameMap f{};
+    const long long mult[3] = {(long long)N * N, N, 1};
+    long long base = 0, sx = 0, sy = 0, sd = 0;
+    for (int i = 0; i < 3; ++i) {
+        const long long M = mult[i];
+        const long long beta = ax[i].mirror ? -1 : 1;
+        if (ax[i].mirror) base += M * (N - 1);
+        if (ax[i].primed == 0) { base += M * beta * (N - 1); sx -= M * beta; }
+        else if (ax[i].primed == 1) { base += M * beta * (N - 1); sy -= M * beta; }
+        else sd += M * beta;
+    }
+    f.base = (int)base; f.sx = (int)sx; f.sy = (int)sy; f.sd = (int)sd;
+    return f;
+}
+
+// ------------------------------------------------------------------ tuning
+struct Tuning {
+    int nx = 0, ny = 0;
+    int kx[6] = {0}, ky[6] = {0};
+    int lds_elems = 16384;  // LDS budget of one work group, in 4-byte elements
+    int waves = 8;          // wavefronts per work group (upper bound)
+};
+
+static void default_split(int n, int* k, int& cnt)
+{
+    if (n <= 5) { k[0] = n; cnt = 1; return; }
+    if (n <= 10) { k[0] = (n + 1) / 2; k[1] = n / 2; cnt = 2; return; }
+    cnt = 0;
+    int left = n;
+    while (left > 0) { const int t = std::min(5, left); k[cnt++] = t; left -= t; }
+}
+
+static Tuning default_tuning(int n)
+{
+    Tuning t;
+    default_split(n, t.kx, t.nx);
+    default_split(n, t.ky, t.ny);
+    return t;
+}
+
+static std::string tuning_to_string(const Tuning& t)
+{
+    std::string s = "x=";
+    for (int i = 0; i < t.nx; ++i) s += (i ? "," : "") + std::to_string(t.kx[i]);
+    s += ";y=";
+    for (int i = 0; i < t.ny; ++i) s += (i ? "," : "") + std::to_string(t.ky[i]);
+    s += ";lds=" + std::to_string(t.lds_elems) + ";waves=" + std::to_string(t.waves);
+    return s;
+}
+
+static bool parse_list(const char* p, int* out, int& cnt, const char** end)
+{
+    cnt = 0;
+    while (*p >= '0' && *p <= '9') {
+        if (cnt >= 6) return false;
+        char* e = nullptr;
+        out[cnt++] = (int)strtol(p, &e, 10);
+        p = e;
+        if (*p == ',') ++p;
+    }
+    *end = p;
+    return cnt > 0;
+}
+
+static bool tuning_from_string(const char* s, int n, Tuning& t)
+{
+    Tuning r;
+    const char* p = s;
+    char* e = nullptr;
+    if (strncmp(p, "x=", 2)) return false;
+    if (!parse_list(p + 2, r.kx, r.nx, &p)) return false;
+    if (strncmp(p, ";y=", 3)) return false;
+    if (!parse_list(p + 3, r.ky, r.ny, &p)) return false;
+    if (strncmp(p, ";lds=", 5)) return false;
+    r.lds_elems = (int)strtol(p + 5, &e, 10);
+    p = e;
+    if (strncmp(p, ";waves=", 7)) return false;
+    r.waves = (int)strtol(p + 7, &e, 10);
+    int sx = 0, sy = 0;
+    for (int i = 0; i < r.nx; ++i) { if (r.kx[i] < 1 || r.kx[i] > 6) return false; sx += r.kx[i]; }
+    for (int i = 0; i < r.ny; ++i) { if (r.ky[i] < 1 || r.ky[i] > 6) return false; sy += r.ky[i]; }
+    if (sx != n || sy != n) return false;
+    if (r.lds_elems < 1024 || r.lds_elems > 40960) return false;
+    if (r.waves < 1 || r.waves > 8) return false;
+    t = r;
+    return true;
+}
+
+static std::mutex g_tune_mu;
+static std::map<std::pair<int, int>, Tuning> g_tuning;  // (N, is_float) -> choice
+
+static Tuning get_tuning(int N, int is_float)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuning.find({N, is_float});
+    if (it != g_tuning.end()) return it->second;
+    const int n = ilog2_exact(N);
+    Tuning t = default_tuning(n);
+    if (const char* path = getenv("DRT3D_TUNE_CACHE")) {
+        if (FILE* fp = fopen(path, "r")) {
+            char line[256];
+            while (fgets(line, sizeof line, fp)) {  // the last matching line wins
+                int fN = 0, ff = 0;
+                char txt[200];
+                if (sscanf(line, "%d %d %199s", &fN, &ff, txt) == 3 && fN == N && ff == is_float) {
+                    Tuning c;
+                    if (tuning_from_string(txt, n, c)) t = c;
+                }
+            }
+            fclose(fp);
+        }
+    }
+    g_tuning[{N, is_float}] = t;
+    return t;
+}
+
+static void put_tuning(int N, int is_float, const Tuning& t)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuning[{N, is_float}] = t;
+}
+
+// ------------------------------------------------------------------ device
+struct DeviceInfo {
+    int cus = 256;
+    int max_lds = 65536;
+    int arch_ok = 0;
+};
+static std::mutex g_dev_mu;
+static std::map<int, DeviceInfo> g_devs;
+
+static int device_info(DeviceInfo& out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_devs.find(dev);
+    if (it == g_devs.end()) {
+        DeviceInfo di;
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, dev));
+        di.cus = prop.multiProcessorCount;
+        di.max_lds = (int)prop.sharedMemPerBlock;
+        di.arch_ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+        if (di.arch_ok && di.max_lds > 65536) {
+            if (set_drt_lds_limit(0, di.max_lds) != hipSuccess || set_drt_lds_limit(1, di.max_lds) != hipSuccess)
+                di.max_lds = 65536;
+            (void)hipGetLastError();
+        }
+        it = g_devs.emplace(dev, di).first;
+    }
+    if (!it->second.arch_ok) return fail(DRT3D_EUNSUPPORTED, "this library is built for gfx950 (MI355X) only");
+    out = it->second;
+    return DRT3D_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes;
+};
+struct ProfSum {
+    double ms = 0, bytes = 0;
+    long long n = 0;
+};
+static std::mutex g_prof_mu;
+static std::atomic<int> g_prof_on{0};
+static std::vector<ProfRec> g_prof_pending;
+static std::map<std::string, ProfSum> g_prof_sum;
+
+static int prof_flush()
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto& r : g_prof_pending) {
+        HIP_TRY(hipEventSynchronize(r.b));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        ProfSum& s = g_prof_sum[r.name];
+        s.ms += ms;
+        s.bytes += r.bytes;
+        s.n += 1;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof_pending.clear();
+    return DRT3D_OK;
+}
+
+// ------------------------------------------------------------------ programs
+enum StepKind { S_DRT = 0, S_DJT = 1, S_TRANSPOSE = 2 };
+
+struct Step {
+    int kind = S_DRT;
+    int key = 0;  // canonical position (batched merge key)
+    std::string name;
+    std::vector<DrtDesc> drt;
+    std::vector<DjtDesc> djt;
+    int waves = 4;     // wavefronts per work group
+    size_t lds = 0;    // dynamic LDS bytes
+    double bytes = 0;  // algorithmic bytes (reads of inputs + writes of outputs)
+    // transpose: out[b][c][r] (+)= in[b][r][c]
+    const void* t_in = nullptr;
+    void* t_out = nullptr;
+    int t_R = 0, t_C = 0, t_batches = 0, t_add = 0;
+};
+
+struct Launch {
+    int kind;
+    std::string name;
+    int first = 0, ndesc = 0;
+    long long total_wg = 0;
+    int block = 64;
+    size_t lds = 0;
+    double bytes = 0;
+    const void* t_in = nullptr;
+    void* t_out = nullptr;
+    int t_R = 0, t_C = 0, t_batches = 0, t_add = 0;
+};
+
+struct Program {
+    int is_float = 0;
+    int persistent = 0;
+    std::vector<DrtDesc> drt;
+    std::vector<DjtDesc> djt;
+    std::vector<Launch> launches;
+    size_t drt_bytes() const { return align256(drt.size() * sizeof(DrtDesc)); }
+    size_t desc_bytes() const { return drt_bytes() + align256(djt.size() * sizeof(DjtDesc)); }
+};
+
+// Append the steps as launches, in order (single calls) or merged by key
+// (batched calls: all steps with the same key form one launch).
+static void build_program(Program& prog, const std::vector<std::vector<Step>>& per_volume, bool merge)
+{
+    std::vector<const Step*> order;
+    if (!merge) {
+        for (auto& v : per_volume)
+            for (auto& s : v) order.push_back(&s);
+    } else {
+        std::map<int, std::vector<const Step*>> bykey;
+        for (auto& v : per_volume)
+            for (auto& s : v) bykey[s.key].push_back(&s);
+        for (auto& kv : bykey)
+            for (auto* s : kv.second) order.push_back(s);
+    }
+    size_t i = 0;
+    while (i < order.size()) {
+        const Step* s0 = order[i];
+        size_t j = i + 1;
+        if (merge && s0->kind != S_TRANSPOSE)
+            while (j < order.size() && order[j]->key == s0->key && order[j]->kind == s0->kind) ++j;
+        Launch L;
+        L.kind = s0->kind;
+        L.name = s0->name;
+        if (s0->kind == S_TRANSPOSE) {
+            L.t_in = s0->t_in; L.t_out = s0->t_out; L.t_R = s0->t_R; L.t_C = s0->t_C;
+            L.t_batches = s0->t_batches; L.t_add = s0->t_add; L.bytes = s0->bytes;
+            prog.launches.push_back(L);
+            i = j;
+            continue;
+        }
+        int waves = 1;
+        size_t lds = 0;
+        double bytes = 0;
+        long long wg = 0;
+        L.first = s0->kind == S_DRT ? (int)prog.drt.size() : (int)prog.djt.size();
+        for (size_t q = i; q < j; ++q) {
+            const Step* s = order[q];
+            waves = std::max(waves, s->waves);
+            lds = std::max(lds, s->lds);
+            bytes += s->bytes;
+            if (s->kind == S_DRT) {
+                for (DrtDesc d : s->drt) {
+                    d.wg_begin = wg;
+                    wg += (long long)d.nslots * d.groups * d.ntiles;
+                    prog.drt.push_back(d);
+                }
+            } else {
+                for (DjtDesc d : s->djt) {
+                    d.wg_begin = wg;
+                    wg += (long long)d.nslots * d.groups * d.nbands;
+                    prog.djt.push_back(d);
+                }
+            }
+        }
+        L.ndesc = (s0->kind == S_DRT ? (int)prog.drt.size() : (int)prog.djt.size()) - L.first;
+        L.total_wg = wg;
+        L.block = 64 * waves;
+        L.lds = lds;
+        L.bytes = bytes;
+        prog.launches.push_back(L);
+        i = j;
+    }
+}
+
+// Pinned staging ring for descriptor uploads (reused once its copy is done).
+struct Staging {
+    static constexpr int kSlots = 16;
+    void* buf[kSlots] = {nullptr};
+    size_t cap[kSlots] = {0};
+    hipEvent_t ev[kSlots] = {nullptr};
+    int next = 0;
+};
+static std::mutex g_stage_mu;
+static std::map<int, Staging> g_stage;
+
+static int upload_descs(const Program& p, void* d_area, hipStream_t s)
+{
+    const size_t bytes = p.desc_bytes();
+    if (!bytes) return DRT3D_OK;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    Staging& st = g_stage[dev];
+    const int i = st.next;
+    st.next = (st.next + 1) % Staging::kSlots;
+    if (st.ev[i]) HIP_TRY(hipEventSynchronize(st.ev[i]));
+    else HIP_TRY(hipEventCreateWithFlags(&st.ev[i], hipEventDisableTiming));
+    if (st.cap[i] < bytes) {
+        if (st.buf[i]) HIP_TRY(hipHostFree(st.buf[i]));
+        st.buf[i] = nullptr;
+        st.cap[i] = 0;
+        const size_t c = std::max(bytes, (size_t)1 << 20);
+        HIP_TRY(hipHostMalloc(&st.buf[i], c, hipHostMallocDefault));
+        st.cap[i] = c;
+    }
+    char* h = (char*)st.buf[i];
+    memset(h, 0, bytes);
+    if (!p.drt.empty()) memcpy(h, p.drt.data(), p.drt.size() * sizeof(DrtDesc));
+    if (!p.djt.empty()) memcpy(h + p.drt_bytes(), p.djt.data(), p.djt.size() * sizeof(DjtDesc));
+    HIP_TRY(hipMemcpyAsync(d_area, h, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(st.ev[i], s));
+    return DRT3D_OK;
+}
+
+static int grid_for(long long total_wg, const DeviceInfo& di, int persistent)
+{
+    const long long cap = persistent ? (long long)di.cus * 8 : (1LL << 30);
+    return (int)std::max(1LL, std::min(total_wg, cap));
+}
+
+static int run_launches(const Program& p, void* d_area, hipStream_t s, const DeviceInfo& di)
+{
+    const DrtDesc* d_drt = reinterpret_cast<const DrtDesc*>(d_area);
+    const DjtDesc* d_djt = reinterpret_cast<const DjtDesc*>((char*)d_area + p.drt_bytes());
+    const bool prof = g_prof_on.load() != 0;
+    for (const Launch& L : p.launches) {
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (prof) {
+            HIP_TRY(hipEventCreate(&ea));
+            HIP_TRY(hipEventCreate(&eb));
+            HIP_TRY(hipEventRecord(ea, s));
+        }
+        hipError_t e = hipSuccess;
+        if (L.kind == S_DRT) {
+            if (L.lds > (size_t)di.max_lds)
+                return fail(DRT3D_EINVAL, "%s needs %zu bytes of LDS, the device allows %d", L.name.c_str(), L.lds,
+                            di.max_lds);
+            e = launch_drt_pass(p.is_float, d_drt + L.first, L.ndesc, L.total_wg, L.block,
+                                grid_for(L.total_wg, di, p.persistent), L.lds, s);
+        } else if (L.kind == S_DJT) {
+            e = launch_djt_stage(p.is_float, d_djt + L.first, L.ndesc, L.total_wg, L.block,
+                                 grid_for(L.total_wg, di, p.persistent), s);
+        } else {
+            e = launch_transpose(p.is_float, L.t_in, L.t_out, L.t_R, L.t_C, L.t_batches, L.t_add, s);
+        }
+        if (e != hipSuccess)
+            return fail(DRT3D_EHIP, "launch of %s failed: %s", L.name.c_str(), hipGetErrorString(e));
+        if (prof) {
+            HIP_TRY(hipEventRecord(eb, s));
+            std::lock_guard<std::mutex> lk(g_prof_mu);
+            g_prof_pending.push_back({L.name, ea, eb, L.bytes});
+        }
+    }
+    return DRT3D_OK;
+}
+
+// ------------------------------------------------------------------ DRT plan
+struct PassGeom {
+    int axis, m0, K, idx;  // idx: position among the passes of its axis
+    int E_in, E_out;       // forward extents
+};
+
+static std::vector<PassGeom> drt_passes(int N, const Tuning& t)
+{
+    std::vector<PassGeom> v;
+    int m = 0;
+    for (int i = 0; i < t.nx; ++i) {
+        v.push_back({0, m, t.kx[i], i, N + (1 << m) - 1, N + (1 << (m + t.kx[i])) - 1});
+        m += t.kx[i];
+    }
+    m = 0;
+    for (int i = 0; i < t.ny; ++i) {
+        v.push_back({1, m, t.ky[i], i, 2 * N + (1 << m) - 2, 2 * N + (1 << (m + t.ky[i])) - 2});
+        m += t.ky[i];
+    }
+    return v;
+}
+
+// Largest extent of any intermediate (non-final) pass output over every
+// admissible grouping, so that buffer sizes never depend on the tuning.
+static long long max_intermediate_extent(int N)
+{
+    const int n = ilog2_exact(N);
+    if (n <= 1) return 2LL * N - 1;
+    return 2LL * N + (1LL << (n - 1)) - 2;  // a y-group ending at stage n-1
+}
+
+static long long drt_stage_elems_per_dod(int N) { return (long long)N * N * round4(max_intermediate_extent(N)); }
+
+static const long long kStageBudget = 8LL << 30;  // stage-buffer bytes of one single-volume call
+
+static int chunk_size(long long per_dod_bytes, int ndod)
+{
+    const long long c = std::max(1LL, kStageBudget / std::max(1LL, per_dod_bytes));
+    return (int)std::min<long long>(ndod, c);
+}
+
+// Tile choice of one pass: T (tile width, in the displacement the pass
+// writes), H (halo), L (LDS column length), ntiles.
+static bool choose_tiles(const PassGeom& g, int adjoint, int lds_elems, int& T, int& H, int& L, int& ntiles)
+{
+    const int ns = 1 << g.K;
+    const int E_tile = adjoint ? g.E_in : g.E_out;  // extent written
+    if ((long long)ns * round4(g.E_out) <= lds_elems) {
+        T = E_tile; H = 0; L = g.E_out; ntiles = 1;
+        return true;
+    }
+    H = (1 << g.m0) * ((1 << g.K) - 1);
+    const int tmax = ((lds_elems / ns) - H) & ~3;
+    if (tmax < 16) return false;
+    ntiles = (E_tile + tmax - 1) / tmax;
+    T = (int)round4((E_tile + ntiles - 1) / ntiles);
+    L = T + H;
+    return (long long)ns * round4(L) <= lds_elems;
+}
+
+static const int kKeyTransY = 0, kKeyTransX = 1, kKeyPass = 10, kKeyRound = 40, kKeyCombine = 60;
+
+struct DrtIO {
+    const void* in;   // forward: volume; adjoint: projection
+    void* out;        // forward: projection; adjoint: volume
+    char* ws;         // workspace base for this volume's buffers (after descriptors)
+};
+
+static size_t drt_ws_volume_bytes(int N, uint32_t mask, int elem, int adjoint, int chunked)
+{
+    const int nd = popcount12(mask);
+    bool g1 = false, g2 = false;
+    for (int k = 0; k < 12; ++k)
+        if ((mask >> k) & 1) { g1 |= drt_group(k) == 1; g2 |= drt_group(k) == 2; }
+    const size_t vol = (size_t)N * N * N * elem;
+    const long long per = drt_stage_elems_per_dod(N) * elem;
+    const int c = chunked ? chunk_size(2 * per, nd) : nd;
+    size_t b = 0;
+    b += g1 ? align256(vol) : 0;  // V_Y (forward) or the y-group accumulator (adjoint)
+    b += g2 ? align256(vol) : 0;
+    b += 2 * align256((size_t)c * per);
+    (void)adjoint;
+    return b;
+}
+
+// Steps of one DRT forward or adjoint over the dodecants of `mask`.
+static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_float, int adjoint, int chunked,
+                     const Tuning& t, const DrtIO& io)
+{
+    const int n = ilog2_exact(N);
+    const int elem = 4;
+    const int nd = popcount12(mask);
+    int dods[12], nd2 = 0;
+    for (int k = 0; k < 12; ++k)
+        if ((mask >> k) & 1) dods[nd2++] = k;
+    bool has[3] = {false, false, false};
+    for (int i = 0; i < nd; ++i) has[drt_group(dods[i])] = true;
+    const size_t vol_bytes = (size_t)N * N * N * elem;
+    const long long per = drt_stage_elems_per_dod(N);
+    const int chunk = chunked ? chunk_size(2 * per * elem, nd) : nd;
+
+    char* w = io.ws;
+    void* V[3] = {nullptr, nullptr, nullptr};
+    V[0] = adjoint ? io.out : const_cast<void*>(io.in);
+    if (has[1]) { V[1] = w; w += align256(vol_bytes); }
+    if (has[2]) { V[2] = w; w += align256(vol_bytes); }
+    void* S[2];
+    S[0] = w; w += align256((size_t)chunk * per * elem);
+    S[1] = w;
+
+    const long long out_pitch = 3LL * N - 2;
+    const long long slot_out = (long long)N * N * out_pitch;
+
+    // forward: the y- and x-normal copies of the volume
+    if (!adjoint) {
+        if (has[1]) {  // V_Y[x][z][y] = vol[x][y][z]
+            Step s; s.kind = S_TRANSPOSE; s.key = kKeyTransY; s.name = "transpose_in";
+            s.t_in = io.in; s.t_out = V[1]; s.t_R = N; s.t_C = N; s.t_batches = N; s.t_add = 0;
+            s.bytes = 2.0 * vol_bytes;
+            steps.push_back(s);
+        }
+        if (has[2]) {  // V_X[(y,z)][x] = vol[x][(y,z)]
+            Step s; s.kind = S_TRANSPOSE; s.key = kKeyTransX; s.name = "transpose_in";
+            s.t_in = io.in; s.t_out = V[2]; s.t_R = N; s.t_C = N * N; s.t_batches = 1; s.t_add = 0;
+            s.bytes = 2.0 * vol_bytes;
+            steps.push_back(s);
+        }
+    }
+
+    const std::vector<PassGeom> P = drt_passes(N, t);
+    const int np = (int)P.size();
+    bool seen_group[3] = {false, false, false};
+    for (int c0 = 0; c0 < nd; c0 += chunk) {
+        const int ns = std::min(chunk, nd - c0);
+        for (int step = 0; step < np; ++step) {
+            const int pi = adjoint ? np - 1 - step : step;
+            const PassGeom& g = P[pi];
+            DrtDesc d{};
+            d.N = N; d.n = n; d.axis = g.axis; d.m0 = g.m0; d.K = g.K; d.adjoint = adjoint;
+            int T, H, L, ntl;
+            if (!choose_tiles(g, adjoint, t.lds_elems, T, H, L, ntl))
+                return fail(DRT3D_EINVAL, "tuning %s cannot fit pass (axis %d, m0 %d, K %d) in LDS",
+                            tuning_to_string(t).c_str(), g.axis, g.m0, g.K);
+            d.T = T; d.H = H; d.L = L; d.Lp = (int)round4(L); d.ntiles = ntl;
+            d.groups = (N * N) >> g.K;
+            d.nslots = ns;
+            d.E_in = adjoint ? g.E_out : g.E_in;
+            d.E_out = adjoint ? g.E_in : g.E_out;
+            for (int s = 0; s < ns; ++s) {
+                d.phys[s] = s;
+                d.fm[s] = drt_frame_map(dods[c0 + s], N);
+            }
+            const bool first = step == 0, last = step == np - 1;
+            if (first && !adjoint) {
+                d.src_mode = 1;
+                for (int i = 0; i < 3; ++i) d.vsrc[i] = V[i];
+            } else if (first) {
+                d.src = (const char*)io.in + (size_t)c0 * slot_out * elem;
+                d.src_slot_stride = slot_out;
+                d.P_in = (int)out_pitch;
+            } else {
+                d.src = S[(step - 1) & 1];
+                d.src_slot_stride = per;
+                d.P_in = (int)round4(d.E_in);
+            }
+            if (last && !adjoint) {
+                d.dst = (char*)io.out + (size_t)c0 * slot_out * elem;
+                d.dst_slot_stride = slot_out;
+                d.P_out = (int)out_pitch;
+            } else if (last) {
+                d.dst_mode = 1;
+                for (int i = 0; i < 3; ++i) d.vdst[i] = V[i];
+            } else {
+                d.dst = S[step & 1];
+                d.dst_slot_stride = per;
+                d.P_out = (int)round4(d.E_out);
+            }
+            const int waves = std::min(t.waves, std::max(1, 1 << (g.K - 1)));
+            const size_t lds = (size_t)(1 << g.K) * d.Lp * elem;
+            const double cols = (double)N * N;
+            char nm[32];
+            snprintf(nm, sizeof nm, "drt_%s_%c%d", adjoint ? "adj" : "fwd", g.axis ? 'y' : 'x', g.idx + 1);
+            if (!(last && adjoint)) {
+                Step s; s.kind = S_DRT; s.key = kKeyPass + step; s.name = nm;
+                s.waves = waves; s.lds = lds;
+                s.bytes = (double)ns * cols * elem * (first && !adjoint ? N + d.E_out : d.E_in + d.E_out);
+                s.drt.push_back(d);
+                steps.push_back(s);
+            } else {
+                // slots of one frame group add into the same volume: one
+                // launch per rank within the group keeps the adds ordered
+                int rank[kMaxSlots], cnt[3] = {0, 0, 0}, nr = 0;
+                for (int s = 0; s < ns; ++s) {
+                    rank[s] = cnt[d.fm[s].group]++;
+                    nr = std::max(nr, rank[s] + 1);
+                }
+                for (int r = 0; r < nr; ++r) {
+                    DrtDesc e = d;
+                    int k = 0;
+                    for (int s = 0; s < ns; ++s) {
+                        if (rank[s] != r) continue;
+                        const int grp = d.fm[s].group;
+                        e.phys[k] = s;
+                        e.fm[k] = d.fm[s];
+                        e.accum[k] = seen_group[grp] ? 1 : 0;
+                        seen_group[grp] = true;
+                        ++k;
+                    }
+                    e.nslots = k;
+                    Step s; s.kind = S_DRT; s.key = kKeyRound + r; s.name = nm;
+                    s.waves = waves; s.lds = lds;
+                    double acc_reads = 0;
+                    for (int q = 0; q < k; ++q) acc_reads += e.accum[q] ? (double)N : 0.0;
+                    s.bytes = cols * elem * ((double)k * (d.E_in + d.E_out) + acc_reads);
+                    s.drt.push_back(e);
+                    steps.push_back(s);
+                }
+            }
+        }
+    }
+    if (adjoint) {
+        // accumulators of the y- and x-normal groups back into [x][y][z]
+        bool written = has[0];
+        if (has[1]) {
+            Step s; s.kind = S_TRANSPOSE; s.key = kKeyCombine; s.name = "transpose_out";
+            s.t_in = V[1]; s.t_out = io.out; s.t_R = N; s.t_C = N; s.t_batches = N; s.t_add = written;
+            s.bytes = (written ? 3.0 : 2.0) * vol_bytes;
+            steps.push_back(s);
+            written = true;
+        }
+        if (has[2]) {
+            Step s; s.kind = S_TRANSPOSE; s.key = kKeyCombine + 1; s.name = "transpose_out";
+            s.t_in = V[2]; s.t_out = io.out; s.t_R = N * N; s.t_C = N; s.t_batches = 1; s.t_add = written;
+            s.bytes = (written ? 3.0 : 2.0) * vol_bytes;
+            steps.push_back(s);
+        }
+    }
+    return DRT3D_OK;
+}
+
+// ------------------------------------------------------------------ DJT plan
+static long long djt_extent(int N, int m) { return (long long)N + (1LL << m) - 1; }
+
+// Elements of the stage-m -> m+1 output of one dodecant (m < n-1).
+static long long djt_stage_out_elems(int N, int m)
+{
+    const long long E = djt_extent(N, m + 1);
+    return (long long)N * (2LL << m) * E * E;
+}
+
+static void djt_buffer_elems(int N, long long& a, long long& b)
+{
+    const int n = ilog2_exact(N);
+    a = 0; b = 0;
+    for (int m = 0; m + 1 < n; ++m) {
+        const long long e = djt_stage_out_elems(N, m);
+        if (m & 1) b = std::max(b, e); else a = std::max(a, e);
+    }
+}
+
+static size_t djt_ws_volume_bytes(int N, uint32_t mask, int elem, int chunked)
+{
+    long long a, b;
+    djt_buffer_elems(N, a, b);
+    const int nd = popcount12(mask);
+    const int c = chunked ? chunk_size((a + b) * elem, nd) : nd;
+    return align256((size_t)c * a * elem) + align256((size_t)c * b * elem);
+}
+
+static int djt_steps(std::vector<Step>& steps, int N, uint32_t mask, int chunked, const DrtIO& io)
+{
+    const int n = ilog2_exact(N);
+    const int elem = 4;
+    const int nd = popcount12(mask);
+    int dods[12], q = 0;
+    for (int k = 0; k < 12; ++k)
+        if ((mask >> k) & 1) dods[q++] = k;
+    long long A, B;
+    djt_buffer_elems(N, A, B);
+    const int chunk = chunked ? chunk_size((A + B) * elem, nd) : nd;
+    char* w = io.ws;
+    void* buf[2];
+    buf[0] = w; w += align256((size_t)chunk * A * elem);
+    buf[1] = w;
+    const long long Ef = 2LL * N - 1;
+    const long long slot_out = (long long)N * N * Ef * Ef;
+    for (int c0 = 0; c0 < nd; c0 += chunk) {
+        const int ns = std::min(chunk, nd - c0);
+        for (int m = 0; m < n; ++m) {
+            DjtDesc d{};
+            d.N = N; d.n = n; d.m = m;
+            d.E_in = (int)djt_extent(N, m);
+            d.E_out = (int)djt_extent(N, m + 1);
+            d.groups = (N >> (m + 1)) << (2 * m);
+            d.rows_per_band = 16;
+            d.nbands = (d.E_out + d.rows_per_band - 1) / d.rows_per_band;
+            d.nslots = ns;
+            for (int s = 0; s < ns; ++s) d.fm[s] = djt_frame_map(dods[c0 + s], N);
+            if (m == 0) { d.src_mode = 1; d.src = io.in; }
+            else { d.src = buf[(m - 1) & 1]; d.src_slot_stride = (m - 1) & 1 ? B : A; }
+            if (m == n - 1) {
+                d.dst = (char*)io.out + (size_t)c0 * slot_out * elem;
+                d.dst_slot_stride = slot_out;
+                d.final_stage = 1;
+            } else {
+                d.dst = buf[m & 1];
+                d.dst_slot_stride = m & 1 ? B : A;
+            }
+            Step s; s.kind = S_DJT; s.key = kKeyPass + m; s.name = m == n - 1 ? "djt_stage_last" : "djt_stage";
+            s.waves = 4;
+            const double in_e = m == 0 ? (double)N * N * N : (double)N * (1LL << m) * d.E_in * d.E_in;
+            const double out_e = (double)N * (2LL << m) * d.E_out * d.E_out;
+            s.bytes = (double)ns * elem * (in_e + out_e);
+            s.djt.push_back(d);
+            steps.push_back(s);
+        }
+    }
+    return DRT3D_OK;
+}
+
+// ------------------------------------------------------------------ graphs
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+};
+static std::mutex g_graph_mu;
+static std::map<std::string, GraphEntry> g_graphs;
+
+static std::string program_signature(const Program& p, void* d_area)
+{
+    std::string sig;
+    char buf[128];
+    snprintf(buf, sizeof buf, "%p|%d|", d_area, p.is_float);
+    sig += buf;
+    for (const Launch& L : p.launches) {
+        snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%zu:%p:%p:%d:%d:%d:%d;", L.kind, L.first, L.ndesc, L.total_wg,
+                 L.block, L.lds, L.t_in, L.t_out, L.t_R, L.t_C, L.t_batches, L.t_add);
+        sig += buf;
+    }
+    return sig;
+}
+
+// Replays a cached graph of the program's launches, capturing it on a miss.
+// Descriptors are uploaded before the replay; kernel arguments only hold the
+// descriptor area, so a graph stays valid while the workspace does.
+static int run_graph(const Program& p, void* d_area, hipStream_t s, const DeviceInfo& di)
+{
+    const std::string sig = program_signature(p, d_area);
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(sig);
+    if (it == g_graphs.end()) {
+        hipStream_t cs = s;
+        bool own = false;
+        if (s == nullptr) {  // the legacy default stream cannot be captured
+            HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            own = true;
+        }
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        const int rc = run_launches(p, d_area, cs, di);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &graph);
+        if (own) (void)hipStreamDestroy(cs);
+        if (rc != DRT3D_OK) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+        if (e != hipSuccess) return fail(DRT3D_EHIP, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        GraphEntry ge;
+        const hipError_t e2 = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) return fail(DRT3D_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e2));
+        it = g_graphs.emplace(sig, ge).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second.exec, s));
+    return DRT3D_OK;
+}
+
+// ------------------------------------------------------------------ execution
+static int execute(Program& prog, void* ws, hipStream_t s, const DeviceInfo& di, int use_graph)
+{
+    TRY(upload_descs(prog, ws, s));
+    const bool prof = g_prof_on.load() != 0;
+    if (use_graph && !prof) return run_graph(prog, ws, s, di);
+    return run_launches(prog, ws, s, di);
+}
+
+// ------------------------------------------------------------------ validation
+static int check_common(int N, uint32_t mask, int dtype)
+{
+    if (ilog2_exact(N) < 1) return fail(DRT3D_EINVAL, "N must be a power of two in [2, %d], got %d", DRT3D_MAX_N, N);
+    if (mask == 0 || (mask & ~DRT3D_ALL)) return fail(DRT3D_EINVAL, "mask must be a nonzero 12-bit set, got 0x%x", mask);
+    if (dtype != DRT3D_I32 && dtype != DRT3D_F32) return fail(DRT3D_EINVAL, "unsupported dtype %d", dtype);
+    return DRT3D_OK;
+}
+
+static int check_ptr(const void* p, const char* what)
+{
+    if (!p) return fail(DRT3D_EINVAL, "%s is NULL", what);
+    if ((uintptr_t)p & 15) return fail(DRT3D_EINVAL, "%s is not 16-byte aligned", what);
+    return DRT3D_OK;
+}
+
+static int check_ws(void* ws, size_t have, size_t need)
+{
+    if (!ws) return fail(DRT3D_EINVAL, "workspace is NULL");
+    if ((uintptr_t)ws & 255) return fail(DRT3D_EINVAL, "workspace is not 256-byte aligned");
+    if (have < need) return fail(DRT3D_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", have, need);
+    return DRT3D_OK;
+}
+
+// Descriptor area bounds: one DrtDesc/DjtDesc per step, per volume.
+static size_t desc_area_bytes(int kind, int N, uint32_t mask, int chunked)
+{
+    const int nd = popcount12(mask);
+    const int n = ilog2_exact(N);
+    size_t cnt;
+    if (kind == S_DJT) {
+        long long A, B;
+        djt_buffer_elems(N, A, B);
+        const int c = chunked ? chunk_size((A + B) * 4, nd) : nd;
+        cnt = (size_t)((nd + c - 1) / c) * n;
+        return align256(cnt * sizeof(DjtDesc)) + 256;
+    }
+    const int c = chunked ? chunk_size(2 * drt_stage_elems_per_dod(N) * 4, nd) : nd;
+    cnt = (size_t)((nd + c - 1) / c) * (2 * n + 4);  // passes (<= 2n) + adjoint rounds
+    return align256(cnt * sizeof(DrtDesc)) + 256;
+}
+
+}  // namespace drt3d
+
+// ======================================================================= ABI
+using namespace drt3d;
+
+extern "C" {
+
+const char* drt3d_last_error(void) { return g_last_error.c_str(); }
+int drt3d_abi_version(void) { return DRT3D_ABI_VERSION; }
+
+size_t drt3d_out_elems(int N, uint32_t mask)
+{
+    if (ilog2_exact(N) < 1 || mask == 0 || (mask & ~DRT3D_ALL)) return 0;
+    return (size_t)popcount12(mask) * N * N * (3 * (size_t)N - 2);
+}
+
+size_t djt3d_out_elems(int N, uint32_t mask)
+{
+    if (ilog2_exact(N) < 1 || mask == 0 || (mask & ~DRT3D_ALL)) return 0;
+    return (size_t)popcount12(mask) * N * N * (2 * (size_t)N - 1) * (2 * (size_t)N - 1);
+}
+
+size_t drt3d_workspace_bytes(int N, uint32_t mask, int dtype)
+{
+    if (check_common(N, mask, dtype) != DRT3D_OK) return 0;
+    return desc_area_bytes(S_DRT, N, mask, 1) + drt_ws_volume_bytes(N, mask, 4, 0, 1);
+}
+
+size_t drt3d_adjoint_workspace_bytes(int N, uint32_t mask, int dtype)
+{
+    if (check_common(N, mask, dtype) != DRT3D_OK) return 0;
+    return desc_area_bytes(S_DRT, N, mask, 1) + drt_ws_volume_bytes(N, mask, 4, 1, 1);
+}
+
+size_t djt3d_workspace_bytes(int N, uint32_t mask, int dtype)
+{
+    if (check_common(N, mask, dtype) != DRT3D_OK) return 0;
+    return desc_area_bytes(S_DJT, N, mask, 1) + djt_ws_volume_bytes(N, mask, 4, 1);
+}
+
+static size_t batched_ws(int kind, int adjoint, int count, const int* Ns, uint32_t mask, int dtype)
+{
+    if (count < 1 || !Ns) return 0;
+    size_t d = 0, v = 0;
+    for (int i = 0; i < count; ++i) {
+        if (check_common(Ns[i], mask, dtype) != DRT3D_OK) return 0;
+        d += desc_area_bytes(kind, Ns[i], mask, 0);
+        v += kind == S_DJT ? djt_ws_volume_bytes(Ns[i], mask, 4, 0) : drt_ws_volume_bytes(Ns[i], mask, 4, adjoint, 0);
+    }
+    return align256(d) + v;
+}
+
+size_t drt3d_forward_batched_workspace_bytes(int count, const int* Ns, uint32_t mask, int dtype)
+{
+    return batched_ws(S_DRT, 0, count, Ns, mask, dtype);
+}
+size_t drt3d_adjoint_batched_workspace_bytes(int count, const int* Ns, uint32_t mask, int dtype)
+{
+    return batched_ws(S_DRT, 1, count, Ns, mask, dtype);
+}
+size_t djt3d_forward_batched_workspace_bytes(int count, const int* Ns, uint32_t mask, int dtype)
+{
+    return batched_ws(S_DJT, 0, count, Ns, mask, dtype);
+}
+
+// One volume, DRT forward or adjoint.
+static int drt_single(const void* in, void* out, int N, uint32_t mask, int dtype, void* ws, size_t ws_bytes,
+                      void* stream, int adjoint)
+{
+    TRY(check_common(N, mask, dtype));
+    TRY(check_ptr(in, adjoint ? "proj" : "vol"));
+    TRY(check_ptr(out, adjoint ? "vol_out" : "out"));
+    const size_t need = adjoint ? drt3d_adjoint_workspace_bytes(N, mask, dtype) : drt3d_workspace_bytes(N, mask, dtype);
+    TRY(check_ws(ws, ws_bytes, need));
+    DeviceInfo di;
+    TRY(device_info(di));
+    const int is_float = dtype == DRT3D_F32;
+    const Tuning t = get_tuning(N, is_float);
+    DrtIO io{in, out, (char*)ws + desc_area_bytes(S_DRT, N, mask, 1)};
+    std::vector<std::vector<Step>> vols(1);
+    TRY(drt_steps(vols[0], N, mask, is_float, adjoint, 1, t, io));
+    Program prog;
+    prog.is_float = is_float;
+    build_program(prog, vols, false);
+    if (prog.desc_bytes() > desc_area_bytes(S_DRT, N, mask, 1))
+        return fail(DRT3D_EINVAL, "internal: descriptor area too small");
+    return execute(prog, ws, (hipStream_t)stream, di, 0);
+}
+
+int drt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype, void* workspace,
+                  size_t workspace_bytes, void* stream)
+{
+    return drt_single(vol, out, N, mask, dtype, workspace, workspace_bytes, stream, 0);
+}
+
+int drt3d_adjoint(const void* proj, void* vol_out, int N, uint32_t mask, int dtype, void* workspace,
+                  size_t workspace_bytes, void* stream)
+{
+    return drt_single(proj, vol_out, N, mask, dtype, workspace, workspace_bytes, stream, 1);
+}
+
+int djt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype, void* workspace,
+                  size_t workspace_bytes, void* stream)
+{
+    TRY(check_common(N, mask, dtype));
+    TRY(check_ptr(vol, "vol"));
+    TRY(check_ptr(out, "out"));
+    TRY(check_ws(workspace, workspace_bytes, djt3d_workspace_bytes(N, mask, dtype)));
+    DeviceInfo di;
+    TRY(device_info(di));
+    DrtIO io{vol, out, (char*)workspace + desc_area_bytes(S_DJT, N, mask, 1)};
+    std::vector<std::vector<Step>> vols(1);
+    TRY(djt_steps(vols[0], N, mask, 1, io));
+    Program prog;
+    prog.is_float = dtype == DRT3D_F32;
+    build_program(prog, vols, false);
+    return execute(prog, workspace, (hipStream_t)stream, di, 0);
+}
+
+static int batched(int kind, int adjoint, int count, const void* const* ins, void* const* outs, const int* Ns,
+                   uint32_t mask, int dtype, void* ws, size_t ws_bytes, void* stream)
+{
+    if (count < 1) return fail(DRT3D_EINVAL, "count must be >= 1, got %d", count);
+    if (!ins || !outs || !Ns) return fail(DRT3D_EINVAL, "pointer arrays and Ns must not be NULL");
+    for (int i = 0; i < count; ++i) {
+        TRY(check_common(Ns[i], mask, dtype));
+        TRY(check_ptr(ins[i], "input"));
+        TRY(check_ptr(outs[i], "output"));
+    }
+    TRY(check_ws(ws, ws_bytes, batched_ws(kind, adjoint, count, Ns, mask, dtype)));
+    DeviceInfo di;
+    TRY(device_info(di));
+    const int is_float = dtype == DRT3D_F32;
+    size_t dsz = 0;
+    for (int i = 0; i < count; ++i) dsz += desc_area_bytes(kind, Ns[i], mask, 0);
+    char* w = (char*)ws + align256(dsz);
+    std::vector<std::vector<Step>> vols(count);
+    for (int i = 0; i < count; ++i) {
+        DrtIO io{ins[i], outs[i], w};
+        if (kind == S_DJT) {
+            TRY(djt_steps(vols[i], Ns[i], mask, 0, io));
+            w += djt_ws_volume_bytes(Ns[i], mask, 4, 0);
+        } else {
+            TRY(drt_steps(vols[i], Ns[i], mask, is_float, adjoint, 0, get_tuning(Ns[i], is_float), io));
+            w += drt_ws_volume_bytes(Ns[i], mask, 4, adjoint, 0);
+        }
+    }
+    Program prog;
+    prog.is_float = is_float;
+    prog.persistent = 1;
+    build_program(prog, vols, true);
+    if (prog.desc_bytes() > align256(dsz)) return fail(DRT3D_EINVAL, "internal: descriptor area too small");
+    const char* g = getenv("DRT3D_GRAPHS");
+    const int use_graph = g ? atoi(g) != 0 : 1;
+    return execute(prog, ws, (hipStream_t)stream, di, use_graph);
+}
+
+int drt3d_forward_batched(int count, const void* const* vols, void* const* outs, const int* Ns, uint32_t mask,
+                          int dtype, void* workspace, size_t workspace_bytes, void* stream)
+{
+    return batched(S_DRT, 0, count, vols, outs, Ns, mask, dtype, workspace, workspace_bytes, stream);
+}
+
+int drt3d_adjoint_batched(int count, const void* const* projs, void* const* vols_out, const int* Ns, uint32_t mask,
+                          int dtype, void* workspace, size_t workspace_bytes, void* stream)
+{
+    return batched(S_DRT, 1, count, projs, vols_out, Ns, mask, dtype, workspace, workspace_bytes, stream);
+}
+
+int djt3d_forward_batched(int count, const void* const* vols, void* const* outs, const int* Ns, uint32_t mask,
+                          int dtype, void* workspace, size_t workspace_bytes, void* stream)
+{
+    return batched(S_DJT, 0, count, vols, outs, Ns, mask, dtype, workspace, workspace_bytes, stream);
+}
+
+// ------------------------------------------------------------------ tuning ABI
+const char* drt3d_tuning_string(int N, int dtype)
+{
+    static thread_local std::string s;
+    if (ilog2_exact(N) < 1 || (dtype != DRT3D_I32 && dtype != DRT3D_F32)) return "";
+    s = tuning_to_string(get_tuning(N, dtype == DRT3D_F32));
+    return s.c_str();
+}
+
+int drt3d_set_tuning(int N, int dtype, const char* text)
+{
+    TRY(check_common(N, DRT3D_ALL, dtype));
+    if (!text) return fail(DRT3D_EINVAL, "tuning text is NULL");
+    Tuning t;
+    if (!tuning_from_string(text, ilog2_exact(N), t)) return fail(DRT3D_EINVAL, "cannot parse tuning '%s'", text);
+    // every pass must fit
+    for (int adj = 0; adj < 2; ++adj)
+        for (const PassGeom& g : drt_passes(N, t)) {
+            int T, H, L, nt;
+            if (!choose_tiles(g, adj, t.lds_elems, T, H, L, nt))
+                return fail(DRT3D_EINVAL, "tuning '%s' does not fit LDS", text);
+        }
+    put_tuning(N, dtype == DRT3D_F32, t);
+    return DRT3D_OK;
+}
+
+static void split_candidates(int n, std::vector<std::vector<int>>& out)
+{
+    out.clear();
+    if (n <= 6) out.push_back({n});
+    for (int a = 1; a < n; ++a)
+        if (a <= 6 && n - a <= 6) out.push_back({a, n - a});
+    if (n >= 6) {
+        const int a = n / 3, b = (n - a) / 2, c = n - a - b;
+        out.push_back({c, b, a});
+    }
+}
+
+int drt3d_autotune(int N, int dtype, const void* vol, void* out, void* workspace, size_t workspace_bytes,
+                   void* stream)
+{
+    TRY(check_common(N, DRT3D_ALL, dtype));
+    TRY(check_ptr(vol, "vol"));
+    TRY(check_ptr(out, "out"));
+    TRY(check_ws(workspace, workspace_bytes, drt3d_workspace_bytes(N, DRT3D_ALL, dtype)));
+    DeviceInfo di;
+    TRY(device_info(di));
+    const int n = ilog2_exact(N);
+    const int is_float = dtype == DRT3D_F32;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ea, eb;
+    HIP_TRY(hipEventCreate(&ea));
+    HIP_TRY(hipEventCreate(&eb));
+    auto time_of = [&](const Tuning& t, float& best_ms) -> int {
+        put_tuning(N, is_float, t);
+        best_ms = 1e30f;
+        for (int r = 0; r < 4; ++r) {
+            HIP_TRY(hipEventRecord(ea, s));
+            TRY(drt3d_forward(vol, out, N, DRT3D_ALL, dtype, workspace, workspace_bytes, stream));
+            HIP_TRY(hipEventRecord(eb, s));
+            HIP_TRY(hipEventSynchronize(eb));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, ea, eb));
+            if (r > 0) best_ms = std::min(best_ms, ms);
+        }
+        return DRT3D_OK;
+    };
+    auto fits = [&](const Tuning& t) {
+        if ((size_t)t.lds_elems * 4 > (size_t)di.max_lds) return false;
+        for (int adj = 0; adj < 2; ++adj)
+            for (const PassGeom& g : drt_passes(N, t)) {
+                int T, H, L, nt;
+                if (!choose_tiles(g, adj, t.lds_elems, T, H, L, nt)) return false;
+            }
+        return true;
+    };
+    Tuning best = get_tuning(N, is_float);
+    if (!fits(best)) best = default_tuning(n);
+    float best_ms;
+    TRY(time_of(best, best_ms));
+    std::vector<std::vector<int>> splits;
+    split_candidates(n, splits);
+    const int lds_opts[] = {8192, 12288, 16384, 20480, 24576, 32768, 40960};
+    const int wave_opts[] = {2, 4, 8};
+    for (int round = 0; round < 2; ++round) {
+        for (int dim = 0; dim < 4; ++dim) {
+            std::vector<Tuning> cands;
+            if (dim == 0 || dim == 1) {
+                for (auto& sp : splits) {
+                    Tuning c = best;
+                    int* k = dim == 0 ? c.kx : c.ky;
+                    int& cnt = dim == 0 ? c.nx : c.ny;
+                    cnt = (int)sp.size();
+                    for (int i = 0; i < cnt; ++i) k[i] = sp[i];
+                    cands.push_back(c);
+                }
+            } else if (dim == 2) {
+                for (int l : lds_opts) { Tuning c = best; c.lds_elems = l; cands.push_back(c); }
+            } else {
+                for (int w : wave_opts) { Tuning c = best; c.waves = w; cands.push_back(c); }
+            }
+            for (const Tuning& c : cands) {
+                if (!fits(c) || tuning_to_string(c) == tuning_to_string(best)) continue;
+                float ms;
+                TRY(time_of(c, ms));
+                if (ms < best_ms * 0.98f) { best_ms = ms; best = c; }
+            }
+        }
+    }
+    put_tuning(N, is_float, best);
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    if (const char* path = getenv("DRT3D_TUNE_CACHE")) {
+        if (FILE* fp = fopen(path, "a")) {
+            fprintf(fp, "%d %d %s\n", N, is_float, tuning_to_string(best).c_str());
+            fclose(fp);
+        }
+    }
+    return DRT3D_OK;
+}
+
+// ------------------------------------------------------------------ profiling ABI
+int drt3d_profile_enable(int on)
+{
+    g_prof_on.store(on ? 1 : 0);
+    return DRT3D_OK;
+}
+
+int drt3d_profile_reset(void)
+{
+    TRY(prof_flush());
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_sum.clear();
+    return DRT3D_OK;
+}
+
+int drt3d_pass_times(char* names, double* ms, long long* launches, double* bytes, int cap)
+{
+    TRY(prof_flush());
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    int i = 0;
+    for (auto& kv : g_prof_sum) {
+        if (i < cap) {
+            if (names) {
+                strncpy(names + 32 * i, kv.first.c_str(), 31);
+                names[32 * i + 31] = 0;
+            }
+            if (ms) ms[i] = kv.second.ms;
+            if (launches) launches[i] = kv.second.n;
+            if (bytes) bytes[i] = kv.second.bytes;
+        }
+        ++i;
+    }
+    return i;
+}
+
+// ------------------------------------------------------------------ introspection ABI
+int drt3d_frame_map(int k, int N, int kind, int out[5])
+{
+    if (k < 0 || k > 11 || ilog2_exact(N) < 1 || (kind != 0 && kind != 1) || !out)
+        return fail(DRT3D_EINVAL, "bad arguments to drt3d_frame_map");
+    const FrameMap f = kind == 0 ? drt_frame_map(k, N) : djt_frame_map(k, N);
+    out[0] = f.base; out[1] = f.sx; out[2] = f.sy; out[3] = f.sd; out[4] = kind == 0 ? f.group : 0;
+    return DRT3D_OK;
+}
+
+int drt3d_plan_text(int op, int N, uint32_t mask, int dtype, char* buf, size_t cap)
+{
+    TRY(check_common(N, mask, dtype));
+    if (op < 0 || op > 2) return fail(DRT3D_EINVAL, "op must be 0, 1 or 2");
+    const int is_float = dtype == DRT3D_F32;
+    // placeholder addresses: the plan's shape does not depend on them
+    static char dummy[256] __attribute__((aligned(256)));
+    DrtIO io{dummy, dummy, dummy};
+    std::vector<std::vector<Step>> vols(1);
+    if (op == 2) TRY(djt_steps(vols[0], N, mask, 1, io));
+    else TRY(drt_steps(vols[0], N, mask, is_float, op == 1, 1, get_tuning(N, is_float), io));
+    Program prog;
+    prog.is_float = is_float;
+    build_program(prog, vols, false);
+    std::string txt;
+    char line[256];
+    for (const Launch& L : prog.launches) {
+        snprintf(line, sizeof line, "%s kind=%d wg=%lld block=%d lds=%zu bytes=%.0f\n", L.name.c_str(), L.kind,
+                 L.kind == S_TRANSPOSE ? (long long)((L.t_C + 63) / 64) * ((L.t_R + 63) / 64) * L.t_batches
+                                       : L.total_wg,
+                 L.kind == S_TRANSPOSE ? 256 : L.block, L.lds, L.bytes);
+        txt += line;
+    }
+    if (buf && cap) {
+        strncpy(buf, txt.c_str(), cap - 1);
+        buf[cap - 1] = 0;
+    }
+    return (int)prog.launches.size();
+}
+
+}  // extern "C"
