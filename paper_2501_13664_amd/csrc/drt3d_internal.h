@@ -19,11 +19,12 @@ struct FrameMap {
 
 constexpr int kMaxSlots = 12;
 
-// One DRT pass: K consecutive stages m0..m0+K-1 of eq. (11) restricted to one
-// axis (x: slope s1, or y: slope s2), for every column group of every
-// dodecant slot, forward or adjoint (eq. (17)). Work items are
-// (slot, group, tile) flattened; `wg_begin` is the first flattened index of
-// this descriptor inside its launch.
+// One DRT pass: the x-stages mx0..mx0+Kx-1 (slope s1) and the y-stages
+// my0..my0+Ky-1 (slope s2) of eq. (11), forward or adjoint (eq. (17)), for
+// every column group of every dodecant slot. A group is the 2^Kx x 2^Ky
+// columns that exchange data in these stages. Work items are
+// (slot, group, displacement tile) flattened; `wg_begin` is the first
+// flattened index of this descriptor inside its launch.
 struct DrtDesc {
     long long wg_begin;
     long long src_slot_stride, dst_slot_stride;  // elements between slots
@@ -31,11 +32,12 @@ struct DrtDesc {
     void* dst;                                   // stage buffer (dst_mode 0)
     const void* vsrc[3];                         // volume layouts (src_mode 1)
     void* vdst[3];                               // volume accumulators (dst_mode 1)
-    int groups, ntiles, nslots;
-    int N, n, axis, m0, K;
+    int groups_x, groups_y, ntiles, nslots;
+    int N, n;
+    int mx0, Kx, my0, Ky;
     int E_in, P_in, E_out, P_out;
-    int T, H, L, Lp;
-    int src_mode, dst_mode, adjoint;
+    int T, H, L, Lp;       // tile width, local halo, LDS column length and pitch
+    int src_mode, dst_mode, adjoint, nt_store;
     int phys[kMaxSlots];   // slot -> slot index inside the src/dst stage buffers
     int accum[kMaxSlots];  // dst_mode 1: add into the volume (1) or overwrite (0)
     FrameMap fm[kMaxSlots];

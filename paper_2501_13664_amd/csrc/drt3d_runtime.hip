@@ -169,52 +169,38 @@ static FrameMap djt_frame_map(int k, int N)
 }
 
 // ------------------------------------------------------------------ tuning
+// A tuning is the pass list (each pass fuses kx x-stages and ky y-stages, the
+// stages of each axis taken in order), the LDS budget of a work group and the
+// number of wavefronts per work group.
 struct Tuning {
-    int nx = 0, ny = 0;
-    int kx[6] = {0}, ky[6] = {0};
-    int lds_elems = 16384;  // LDS budget of one work group, in 4-byte elements
+    int np = 0;
+    int kx[8] = {0}, ky[8] = {0};
+    int lds_elems = 18432;  // LDS budget of one work group, in 4-byte elements (72 KB: two per CU)
     int waves = 8;          // wavefronts per work group (upper bound)
 };
 
-static void default_split(int n, int* k, int& cnt)
-{
-    if (n <= 5) { k[0] = n; cnt = 1; return; }
-    if (n <= 10) { k[0] = (n + 1) / 2; k[1] = n / 2; cnt = 2; return; }
-    cnt = 0;
-    int left = n;
-    while (left > 0) { const int t = std::min(5, left); k[cnt++] = t; left -= t; }
-}
+static const int kMaxPassSlots = 256;  // 2^(kx+ky) columns per group at most
 
+// Default: as few passes as fit 64-column groups, stages spread evenly.
 static Tuning default_tuning(int n)
 {
     Tuning t;
-    default_split(n, t.kx, t.nx);
-    default_split(n, t.ky, t.ny);
+    int P = (n + 2) / 3;  // passes of at most 3 x- and 3 y-stages
+    if (P < 1) P = 1;
+    t.np = P;
+    for (int i = 0; i < P; ++i) {
+        t.kx[i] = n / P + (i < n % P ? 1 : 0);
+        t.ky[i] = t.kx[i];
+    }
     return t;
 }
 
 static std::string tuning_to_string(const Tuning& t)
 {
-    std::string s = "x=";
-    for (int i = 0; i < t.nx; ++i) s += (i ? "," : "") + std::to_string(t.kx[i]);
-    s += ";y=";
-    for (int i = 0; i < t.ny; ++i) s += (i ? "," : "") + std::to_string(t.ky[i]);
+    std::string s = "p=";
+    for (int i = 0; i < t.np; ++i) s += (i ? "," : "") + std::to_string(t.kx[i]) + "." + std::to_string(t.ky[i]);
     s += ";lds=" + std::to_string(t.lds_elems) + ";waves=" + std::to_string(t.waves);
     return s;
-}
-
-static bool parse_list(const char* p, int* out, int& cnt, const char** end)
-{
-    cnt = 0;
-    while (*p >= '0' && *p <= '9') {
-        if (cnt >= 6) return false;
-        char* e = nullptr;
-        out[cnt++] = (int)strtol(p, &e, 10);
-        p = e;
-        if (*p == ',') ++p;
-    }
-    *end = p;
-    return cnt > 0;
 }
 
 static bool tuning_from_string(const char* s, int n, Tuning& t)
@@ -222,19 +208,33 @@ static bool tuning_from_string(const char* s, int n, Tuning& t)
     Tuning r;
     const char* p = s;
     char* e = nullptr;
-    if (strncmp(p, "x=", 2)) return false;
-    if (!parse_list(p + 2, r.kx, r.nx, &p)) return false;
-    if (strncmp(p, ";y=", 3)) return false;
-    if (!parse_list(p + 3, r.ky, r.ny, &p)) return false;
+    if (strncmp(p, "p=", 2)) return false;
+    p += 2;
+    r.np = 0;
+    while (*p >= '0' && *p <= '9') {
+        if (r.np >= 8) return false;
+        r.kx[r.np] = (int)strtol(p, &e, 10);
+        p = e;
+        if (*p != '.') return false;
+        r.ky[r.np] = (int)strtol(p + 1, &e, 10);
+        p = e;
+        ++r.np;
+        if (*p == ',') ++p;
+    }
     if (strncmp(p, ";lds=", 5)) return false;
     r.lds_elems = (int)strtol(p + 5, &e, 10);
     p = e;
     if (strncmp(p, ";waves=", 7)) return false;
     r.waves = (int)strtol(p + 7, &e, 10);
+    if (*e) return false;
     int sx = 0, sy = 0;
-    for (int i = 0; i < r.nx; ++i) { if (r.kx[i] < 1 || r.kx[i] > 6) return false; sx += r.kx[i]; }
-    for (int i = 0; i < r.ny; ++i) { if (r.ky[i] < 1 || r.ky[i] > 6) return false; sy += r.ky[i]; }
-    if (sx != n || sy != n) return false;
+    for (int i = 0; i < r.np; ++i) {
+        if (r.kx[i] < 0 || r.ky[i] < 0 || r.kx[i] + r.ky[i] < 1) return false;
+        if ((1 << (r.kx[i] + r.ky[i])) > kMaxPassSlots) return false;
+        sx += r.kx[i];
+        sy += r.ky[i];
+    }
+    if (r.np < 1 || sx != n || sy != n) return false;
     if (r.lds_elems < 1024 || r.lds_elems > 40960) return false;
     if (r.waves < 1 || r.waves > 8) return false;
     t = r;
@@ -427,7 +427,7 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
             if (s->kind == S_DRT) {
                 for (DrtDesc d : s->drt) {
                     d.wg_begin = wg;
-                    wg += (long long)d.nslots * d.groups * d.ntiles;
+                    wg += (long long)d.nslots * d.groups_x * d.groups_y * d.ntiles;
                     prog.drt.push_back(d);
                 }
             } else {
@@ -532,33 +532,33 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
 
 // ------------------------------------------------------------------ DRT plan
 struct PassGeom {
-    int axis, m0, K, idx;  // idx: position among the passes of its axis
-    int E_in, E_out;       // forward extents
+    int mx0, Kx, my0, Ky;  // stage ranges of the pass
+    int E_in, E_out;       // forward extents: N + (2^mx - 1) + (2^my - 1)
 };
 
 static std::vector<PassGeom> drt_passes(int N, const Tuning& t)
 {
     std::vector<PassGeom> v;
-    int m = 0;
-    for (int i = 0; i < t.nx; ++i) {
-        v.push_back({0, m, t.kx[i], i, N + (1 << m) - 1, N + (1 << (m + t.kx[i])) - 1});
-        m += t.kx[i];
-    }
-    m = 0;
-    for (int i = 0; i < t.ny; ++i) {
-        v.push_back({1, m, t.ky[i], i, 2 * N + (1 << m) - 2, 2 * N + (1 << (m + t.ky[i])) - 2});
-        m += t.ky[i];
+    int mx = 0, my = 0;
+    for (int i = 0; i < t.np; ++i) {
+        PassGeom g;
+        g.mx0 = mx; g.Kx = t.kx[i]; g.my0 = my; g.Ky = t.ky[i];
+        g.E_in = N + (1 << mx) - 1 + (1 << my) - 1;
+        mx += t.kx[i];
+        my += t.ky[i];
+        g.E_out = N + (1 << mx) - 1 + (1 << my) - 1;
+        v.push_back(g);
     }
     return v;
 }
 
 // Largest extent of any intermediate (non-final) pass output over every
-// admissible grouping, so that buffer sizes never depend on the tuning.
+// admissible pass list, so that buffer sizes never depend on the tuning.
 static long long max_intermediate_extent(int N)
 {
     const int n = ilog2_exact(N);
     if (n <= 1) return 2LL * N - 1;
-    return 2LL * N + (1LL << (n - 1)) - 2;  // a y-group ending at stage n-1
+    return 2LL * N + (1LL << (n - 1)) - 2;  // all of one axis, all but one stage of the other
 }
 
 static long long drt_stage_elems_per_dod(int N) { return (long long)N * N * round4(max_intermediate_extent(N)); }
@@ -571,23 +571,39 @@ static int chunk_size(long long per_dod_bytes, int ndod)
     return (int)std::min<long long>(ndod, c);
 }
 
-// Tile choice of one pass: T (tile width, in the displacement the pass
-// writes), H (halo), L (LDS column length), ntiles.
+// Tile choice of one pass: T (tile width of the displacement written), H
+// (local halo), L (LDS column length, a multiple of 64), pad (zeros between
+// LDS columns, covering the largest shift of a step), ntiles. The LDS of a
+// work item is nslot * (L + pad) + pad elements. The adjoint's outputs are
+// skewed by up to `skew`, so it needs extra tiles.
+static int pass_pad(const PassGeom& g)
+{
+    // largest step shift: (2^(Kx-1) - 1) + (2^(Ky-1) - 1) + 2 <= H/2 + 2
+    const int H = ((1 << g.Kx) - 1) + ((1 << g.Ky) - 1);
+    const int need = H / 2 + 2;
+    return need <= 16 ? 16 : need <= 32 ? 32 : 64;
+}
+
+static long long lds_elems_of(int nslot, int L, int pad) { return (long long)nslot * (L + pad) + pad; }
+
 static bool choose_tiles(const PassGeom& g, int adjoint, int lds_elems, int& T, int& H, int& L, int& ntiles)
 {
-    const int ns = 1 << g.K;
-    const int E_tile = adjoint ? g.E_in : g.E_out;  // extent written
-    if ((long long)ns * round4(g.E_out) <= lds_elems) {
-        T = E_tile; H = 0; L = g.E_out; ntiles = 1;
-        return true;
-    }
-    H = (1 << g.m0) * ((1 << g.K) - 1);
-    const int tmax = ((lds_elems / ns) - H) & ~3;
-    if (tmax < 16) return false;
-    ntiles = (E_tile + tmax - 1) / tmax;
-    T = (int)round4((E_tile + ntiles - 1) / ntiles);
-    L = T + H;
-    return (long long)ns * round4(L) <= lds_elems;
+    const int ns = 1 << (g.Kx + g.Ky);
+    if (ns > kMaxPassSlots) return false;
+    H = ((1 << g.Kx) - 1) + ((1 << g.Ky) - 1);
+    const int pad = pass_pad(g);
+    if (H / 2 + 2 > pad) return false;
+    const int E = adjoint ? g.E_in : g.E_out;  // extent written
+    const int skew = adjoint ? ((1 << g.mx0) - 1) * ((1 << g.Kx) - 1) + ((1 << g.my0) - 1) * ((1 << g.Ky) - 1) : 0;
+    const int span = E + skew;
+    const int Lmax = (int)(((lds_elems - pad) / ns - pad) & ~63LL);
+    if (Lmax - H < 16) return false;
+    ntiles = (span + (Lmax - H) - 1) / (Lmax - H);
+    const int Tmin = (span + ntiles - 1) / ntiles;
+    L = (Tmin + H + 63) & ~63;
+    T = L - H;
+    ntiles = (span + T - 1) / T;
+    return lds_elems_of(ns, L, pad) <= lds_elems;
 }
 
 static const int kKeyTransY = 0, kKeyTransX = 1, kKeyPass = 10, kKeyRound = 40, kKeyCombine = 60;
@@ -668,13 +684,14 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             const int pi = adjoint ? np - 1 - step : step;
             const PassGeom& g = P[pi];
             DrtDesc d{};
-            d.N = N; d.n = n; d.axis = g.axis; d.m0 = g.m0; d.K = g.K; d.adjoint = adjoint;
+            d.N = N; d.n = n; d.adjoint = adjoint;
+            d.mx0 = g.mx0; d.Kx = g.Kx; d.my0 = g.my0; d.Ky = g.Ky;
             int T, H, L, ntl;
             if (!choose_tiles(g, adjoint, t.lds_elems, T, H, L, ntl))
-                return fail(DRT3D_EINVAL, "tuning %s cannot fit pass (axis %d, m0 %d, K %d) in LDS",
-                            tuning_to_string(t).c_str(), g.axis, g.m0, g.K);
-            d.T = T; d.H = H; d.L = L; d.Lp = (int)round4(L); d.ntiles = ntl;
-            d.groups = (N * N) >> g.K;
+                return fail(DRT3D_EINVAL, "tuning %s cannot fit pass %d in LDS", tuning_to_string(t).c_str(), pi);
+            d.T = T; d.H = H; d.L = L; d.Lp = L + pass_pad(g); d.ntiles = ntl;
+            d.groups_x = N >> g.Kx;
+            d.groups_y = N >> g.Ky;
             d.nslots = ns;
             d.E_in = adjoint ? g.E_out : g.E_in;
             d.E_out = adjoint ? g.E_in : g.E_out;
@@ -699,6 +716,7 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
                 d.dst = (char*)io.out + (size_t)c0 * slot_out * elem;
                 d.dst_slot_stride = slot_out;
                 d.P_out = (int)out_pitch;
+                d.nt_store = 1;  // the caller's output is not read back here
             } else if (last) {
                 d.dst_mode = 1;
                 for (int i = 0; i < 3; ++i) d.vdst[i] = V[i];
@@ -707,11 +725,12 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
                 d.dst_slot_stride = per;
                 d.P_out = (int)round4(d.E_out);
             }
-            const int waves = std::min(t.waves, std::max(1, 1 << (g.K - 1)));
-            const size_t lds = (size_t)(1 << g.K) * d.Lp * elem;
+            const int K = g.Kx + g.Ky;
+            const int waves = std::min(t.waves, std::max(1, 1 << (K - 1)));
+            const size_t lds = (size_t)lds_elems_of(1 << K, L, pass_pad(g)) * elem;
             const double cols = (double)N * N;
             char nm[32];
-            snprintf(nm, sizeof nm, "drt_%s_%c%d", adjoint ? "adj" : "fwd", g.axis ? 'y' : 'x', g.idx + 1);
+            snprintf(nm, sizeof nm, "drt_%s_p%d", adjoint ? "adj" : "fwd", pi + 1);
             if (!(last && adjoint)) {
                 Step s; s.kind = S_DRT; s.key = kKeyPass + step; s.name = nm;
                 s.waves = waves; s.lds = lds;
@@ -1155,15 +1174,34 @@ int drt3d_set_tuning(int N, int dtype, const char* text)
     return DRT3D_OK;
 }
 
-static void split_candidates(int n, std::vector<std::vector<int>>& out)
+// Distinct orderings of the most even split of n stages into P passes.
+static void even_splits(int n, int P, std::vector<std::vector<int>>& out)
 {
-    out.clear();
-    if (n <= 6) out.push_back({n});
-    for (int a = 1; a < n; ++a)
-        if (a <= 6 && n - a <= 6) out.push_back({a, n - a});
-    if (n >= 6) {
-        const int a = n / 3, b = (n - a) / 2, c = n - a - b;
-        out.push_back({c, b, a});
+    std::vector<int> k(P);
+    for (int i = 0; i < P; ++i) k[i] = n / P + (i < n % P ? 1 : 0);
+    std::sort(k.begin(), k.end());
+    do out.push_back(k); while (std::next_permutation(k.begin(), k.end()));
+}
+
+// Candidate pass lists: 1..4 passes, each axis split as evenly as possible in
+// every distinct order, groups of at most kMaxPassSlots columns.
+static void pass_list_candidates(int n, const Tuning& base, std::vector<Tuning>& out)
+{
+    for (int P = 1; P <= std::min(4, n); ++P) {
+        std::vector<std::vector<int>> xs;
+        even_splits(n, P, xs);
+        for (auto& a : xs)
+            for (auto& b : xs) {
+                Tuning c = base;
+                c.np = P;
+                bool ok = true;
+                for (int i = 0; i < P; ++i) {
+                    c.kx[i] = a[i];
+                    c.ky[i] = b[i];
+                    if ((1 << (a[i] + b[i])) > kMaxPassSlots) ok = false;
+                }
+                if (ok) out.push_back(c);
+            }
     }
 }
 
@@ -1209,27 +1247,16 @@ int drt3d_autotune(int N, int dtype, const void* vol, void* out, void* workspace
     if (!fits(best)) best = default_tuning(n);
     float best_ms;
     TRY(time_of(best, best_ms));
-    std::vector<std::vector<int>> splits;
-    split_candidates(n, splits);
-    const int lds_opts[] = {8192, 12288, 16384, 20480, 24576, 32768, 40960};
-    const int wave_opts[] = {2, 4, 8};
+    const int lds_opts[] = {8192, 12288, 16384, 18432, 24576, 32768, 38912};
+    const int wave_opts[] = {4, 8};
     for (int round = 0; round < 2; ++round) {
-        for (int dim = 0; dim < 4; ++dim) {
+        for (int dim = 0; dim < 3; ++dim) {
             std::vector<Tuning> cands;
-            if (dim == 0 || dim == 1) {
-                for (auto& sp : splits) {
-                    Tuning c = best;
-                    int* k = dim == 0 ? c.kx : c.ky;
-                    int& cnt = dim == 0 ? c.nx : c.ny;
-                    cnt = (int)sp.size();
-                    for (int i = 0; i < cnt; ++i) k[i] = sp[i];
-                    cands.push_back(c);
-                }
-            } else if (dim == 2) {
+            if (dim == 0) pass_list_candidates(n, best, cands);
+            else if (dim == 1)
                 for (int l : lds_opts) { Tuning c = best; c.lds_elems = l; cands.push_back(c); }
-            } else {
+            else
                 for (int w : wave_opts) { Tuning c = best; c.waves = w; cands.push_back(c); }
-            }
             for (const Tuning& c : cands) {
                 if (!fits(c) || tuning_to_string(c) == tuning_to_string(best)) continue;
                 float ms;

@@ -155,3 +155,45 @@ def test_batched_equals_single_int():
     js = api.djt3d_forward_batched(dev[:3])
     for d, j in zip(dev[:3], js):
         assert np.array_equal(j.cpu().numpy(), api.djt3d_forward(d).cpu().numpy())
+
+
+# ------------------------------------------------------------------- tunings
+TUNINGS = {
+    8: ["p=3.3;lds=20480;waves=8", "p=1.1,1.1,1.1;lds=1024;waves=4", "p=2.1,1.2;lds=2048;waves=8",
+        "p=3.0,0.3;lds=4096;waves=2", "p=0.3,3.0;lds=1024;waves=1"],
+    32: ["p=3.3,2.2;lds=20480;waves=8", "p=2.2,3.3;lds=6144;waves=8", "p=1.2,2.1,2.2;lds=2048;waves=4",
+         "p=5.0,0.5;lds=40960;waves=8", "p=4.4,1.1;lds=40960;waves=8", "p=2.3,3.2;lds=8192;waves=4"],
+    64: ["p=3.3,3.3;lds=20480;waves=8", "p=3.3,3.3;lds=6144;waves=8", "p=2.2,2.2,2.2;lds=12288;waves=4",
+         "p=4.3,2.3;lds=16384;waves=8"],
+}
+
+
+@pytest.mark.parametrize("N", sorted(TUNINGS))
+def test_every_tuning_is_bit_exact(N):
+    """Pass lists, LDS budgets (hence tile counts) and wave counts change the
+    schedule, never the int32 result; forward and adjoint both."""
+    api = _api()
+    import torch
+    vol = workloads.uniform_int_cube(N, -99, 99, seed=N + 40)
+    ref = O.wrap_int32(O.rec_drt(vol))
+    rng = np.random.default_rng(N)
+    proj = rng.integers(-50, 50, size=ref.shape).astype(np.int32)
+    ref_adj = O.wrap_int32(O.rec_adj(proj, N))
+    default = api.drt3d_tuning_string(N, torch.int32)
+    try:
+        for t in TUNINGS[N]:
+            announce("tuning N=%d %s" % (N, t))
+            api.drt3d_set_tuning(N, t, torch.int32)
+            assert np.array_equal(api.drt3d_forward(to_dev(vol)).cpu().numpy(), ref), t
+            assert np.array_equal(api.drt3d_adjoint(to_dev(proj)).cpu().numpy(), ref_adj), t
+    finally:
+        api.drt3d_set_tuning(N, default, torch.int32)
+
+
+def test_drt_int_n128_full():
+    api = _api()
+    N = 128
+    vol = workloads.uniform_int_cube(N, 0, 255, seed=5)
+    announce("drt int N=128 full")
+    got = api.drt3d_forward(to_dev(vol)).cpu().numpy()
+    assert np.array_equal(got, O.wrap_int32(O.rec_drt(vol)))
