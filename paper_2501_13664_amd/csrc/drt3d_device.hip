@@ -67,70 +67,396 @@ __device__ __forceinline__ int find_desc_drt(const DrtDesc* __restrict__ descs, 
 // covers the largest shift of the pass.
 __device__ __forceinline__ int slot_offset(int p, int Lp, int pad) { return pad + p * Lp; }
 
+// Raw buffer access with the hardware range check: a buffer resource covers
+// one column (or one volume line) exactly, so reads outside it return 0 and
+// writes outside it are dropped, with no compare in the code. Offsets are in
+// bytes; a negative offset wraps to a huge one and is out of range too.
+constexpr int kBufferConfig = 0x00020000;  // gfx9 raw-buffer dword 3
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const T* base, int elems)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, elems * (int)sizeof(T), kBufferConfig);
+}
+
+__device__ __forceinline__ uint32_t bload(__amdgpu_buffer_rsrc_t r, int off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, uint32_t v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
+}
+
+template <typename T> __device__ __forceinline__ uint32_t to_bits(T v) { return __builtin_bit_cast(uint32_t, v); }
+template <typename T> __device__ __forceinline__ T from_bits(uint32_t v) { return __builtin_bit_cast(T, v); }
+
 // Forward radix-2 step (one stage of one axis) on the pair (s0, s1) with
 // local shift t: s0[l] += s1[l-t], s1[l] = s0_old[l] + s1[l-t-1]. In place,
 // 64-position chunks from the top down: a chunk reads only at or below its
 // own positions, and writes after all of its reads.
-template <typename T>
+template <typename T, int NCH>
 __device__ __forceinline__ void step2_fwd(T* s0, T* s1, int nch, int t, int lane)
 {
-    for (int c = nch - 1; c >= 0; --c) {
-        const int l = 64 * c + lane;
-        const T a = s0[l], b0 = s1[l - t], b1 = s1[l - t - 1];
-        s0[l] = a + b0;
-        s1[l] = a + b1;
+    T* w0 = s0 + lane;
+    T* w1 = s1 + lane;
+    const T* r1 = s1 + lane - t - 1;
+    const int n = NCH ? NCH : nch;
+#pragma unroll
+    for (int c = n - 1; c >= 0; --c) {
+        const T a = w0[64 * c], b1 = r1[64 * c], b0 = r1[64 * c + 1];
+        w0[64 * c] = a + b0;
+        w1[64 * c] = a + b1;
     }
 }
 
 // Forward radix-4 step: x-stage and y-stage of the same index fused, which is
 // the four-term stage map of eq. (11) itself. Slot s_ab receives the slope
 // whose new x bit is a and new y bit is b.
-template <typename T>
+template <typename T, int NCH>
 __device__ __forceinline__ void step4_fwd(T* s00, T* s10, T* s01, T* s11, int nch, int tx, int ty, int lane)
 {
-    const int txy = tx + ty;
-    for (int c = nch - 1; c >= 0; --c) {
-        const int l = 64 * c + lane;
-        const T f00 = s00[l];
-        const T f10a = s10[l - tx], f10b = s10[l - tx - 1];
-        const T f01a = s01[l - ty], f01b = s01[l - ty - 1];
-        const T f11a = s11[l - txy], f11b = s11[l - txy - 1], f11c = s11[l - txy - 2];
+    T* w00 = s00 + lane;
+    T* w10 = s10 + lane;
+    T* w01 = s01 + lane;
+    T* w11 = s11 + lane;
+    const T* r10 = s10 + lane - tx - 1;
+    const T* r01 = s01 + lane - ty - 1;
+    const T* r11 = s11 + lane - tx - ty - 2;
+    const int n = NCH ? NCH : nch;
+#pragma unroll
+    for (int c = n - 1; c >= 0; --c) {
+        const int o = 64 * c;
+        const T f00 = w00[o];
+        const T f10b = r10[o], f10a = r10[o + 1];
+        const T f01b = r01[o], f01a = r01[o + 1];
+        const T f11c = r11[o], f11b = r11[o + 1], f11a = r11[o + 2];
         const T x0 = f00 + f10a, x1 = f00 + f10b;
-        s00[l] = x0 + (f01a + f11a);
-        s10[l] = x1 + (f01a + f11b);
-        s01[l] = x0 + (f01b + f11b);
-        s11[l] = x1 + (f01b + f11c);
+        w00[o] = x0 + (f01a + f11a);
+        w10[o] = x1 + (f01a + f11b);
+        w01[o] = x0 + (f01b + f11b);
+        w11[o] = x1 + (f01b + f11c);
     }
 }
 
 // Adjoint radix-2 step (transpose of step2_fwd), chunks from the bottom up.
-template <typename T>
+template <typename T, int NCH>
 __device__ __forceinline__ void step2_adj(T* s0, T* s1, int nch, int t, int lane)
 {
-    for (int c = 0; c < nch; ++c) {
-        const int l = 64 * c + lane;
-        const T a0 = s0[l], a1 = s1[l], c0 = s0[l + t], c1 = s1[l + t + 1];
-        s0[l] = a0 + a1;
-        s1[l] = c0 + c1;
+    T* w0 = s0 + lane;
+    T* w1 = s1 + lane;
+    const T* r0 = s0 + lane + t;
+    const T* r1 = s1 + lane + t + 1;
+    const int n = NCH ? NCH : nch;
+#pragma unroll
+    for (int c = 0; c < n; ++c) {
+        const int o = 64 * c;
+        const T a0 = w0[o], a1 = w1[o], c0 = r0[o], c1 = r1[o];
+        w0[o] = a0 + a1;
+        w1[o] = c0 + c1;
     }
 }
 
 // Adjoint radix-4 step (transpose of step4_fwd).
-template <typename T>
+template <typename T, int NCH>
 __device__ __forceinline__ void step4_adj(T* s00, T* s10, T* s01, T* s11, int nch, int tx, int ty, int lane)
 {
+    T* w00 = s00 + lane;
+    T* w10 = s10 + lane;
+    T* w01 = s01 + lane;
+    T* w11 = s11 + lane;
     const int txy = tx + ty;
-    for (int c = 0; c < nch; ++c) {
-        const int l = 64 * c + lane;
-        const T c00 = (s00[l] + s10[l]) + (s01[l] + s11[l]);
-        const T c10 = (s00[l + tx] + s10[l + tx + 1]) + (s01[l + tx] + s11[l + tx + 1]);
-        const T c01 = (s00[l + ty] + s10[l + ty]) + (s01[l + ty + 1] + s11[l + ty + 1]);
-        const T c11 = (s00[l + txy] + s10[l + txy + 1]) + (s01[l + txy + 1] + s11[l + txy + 2]);
-        s00[l] = c00;
-        s10[l] = c10;
-        s01[l] = c01;
-        s11[l] = c11;
+    const int n = NCH ? NCH : nch;
+#pragma unroll
+    for (int c = 0; c < n; ++c) {
+        const int o = 64 * c;
+        const T c00 = (w00[o] + w10[o]) + (w01[o] + w11[o]);
+        const T c10 = (w00[o + tx] + w10[o + tx + 1]) + (w01[o + tx] + w11[o + tx + 1]);
+        const T c01 = (w00[o + ty] + w10[o + ty]) + (w01[o + ty + 1] + w11[o + ty + 1]);
+        const T c11 = (w00[o + txy] + w10[o + txy + 1]) + (w01[o + txy + 1] + w11[o + txy + 2]);
+        w00[o] = c00;
+        w10[o] = c10;
+        w01[o] = c01;
+        w11[o] = c11;
     }
+}
+
+// All stages of one pass on the LDS slots (forward or adjoint). x-stage j and
+// y-stage j run together as one radix-4 step while both axes have them; the
+// rest run as radix-2 steps. Each axis keeps its stage order, which is all the
+// in-place slot convention needs.
+template <typename T, int NCH>
+__device__ __forceinline__ void run_stages(T* lds, int Lp, int pad, int nch, int Kx, int Ky, int adjoint, int wave,
+                                           int nwaves, int lane)
+{
+    const int nslot = 1 << (Kx + Ky);
+    const int xmask = (1 << Kx) - 1;
+    const int kmax = Kx > Ky ? Kx : Ky;
+    for (int jj = 0; jj < kmax; ++jj) {
+        const int j = adjoint ? kmax - 1 - jj : jj;
+        const bool hx = j < Kx, hy = j < Ky;
+        const int bx = 1 << j, by = 1 << (Kx + j);
+        if (hx && hy) {
+            const int nq = nslot >> 2;
+            for (int q = wave; q < nq; q += nwaves) {
+                // insert zero bits at positions j (x) and Kx + j (y)
+                int p = ((q >> j) << (j + 1)) | (q & (bx - 1));
+                p = ((p >> (Kx + j)) << (Kx + j + 1)) | (p & (by - 1));
+                const int tx = bitrev(p & (bx - 1), j);
+                const int ty = bitrev((p >> Kx) & (bx - 1), j);
+                T* s00 = lds + slot_offset(p, Lp, pad);
+                if (!adjoint) step4_fwd<T, NCH>(s00, s00 + bx * Lp, s00 + by * Lp, s00 + (bx + by) * Lp, nch, tx, ty, lane);
+                else step4_adj<T, NCH>(s00, s00 + bx * Lp, s00 + by * Lp, s00 + (bx + by) * Lp, nch, tx, ty, lane);
+            }
+        } else {
+            const int bit = hx ? j : Kx + j;
+            const int h = 1 << bit;
+            const int np = nslot >> 1;
+            for (int q = wave; q < np; q += nwaves) {
+                const int p = ((q >> bit) << (bit + 1)) | (q & (h - 1));
+                const int axis_bits = hx ? (p & xmask) : (p >> Kx);
+                const int t = bitrev(axis_bits & ((1 << j) - 1), j);
+                T* s0 = lds + slot_offset(p, Lp, pad);
+                if (!adjoint) step2_fwd<T, NCH>(s0, s0 + h * Lp, nch, t, lane);
+                else step2_adj<T, NCH>(s0, s0 + h * Lp, nch, t, lane);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Geometry of one work item (one column group, one displacement tile, one
+// dodecant slot), shared by its load, stage and store phases.
+struct ItemGeom {
+    int N, n, Kx, Ky, mx0, my0;
+    int sx0, sy0, vhx, vhy;
+    int L, Lp, pad, T, H, d0;
+    int adjoint;
+};
+
+// Column of slot p in its stage buffer (or frame view): block (px, py) for
+// the forward input / adjoint output, slope (bitrev px, bitrev py) for the
+// forward output / adjoint input.
+__device__ __forceinline__ void block_col(const ItemGeom& g, int p, int& c1, int& c2)
+{
+    const int px = p & ((1 << g.Kx) - 1), py = p >> g.Kx;
+    c1 = g.sx0 + (px << g.mx0) + g.vhx;
+    c2 = g.sy0 + (py << g.my0) + g.vhy;
+}
+
+__device__ __forceinline__ void slope_col(const ItemGeom& g, int p, int& c1, int& c2)
+{
+    const int px = p & ((1 << g.Kx) - 1), py = p >> g.Kx;
+    c1 = bitrev(px, g.Kx) + (g.sx0 << g.Kx) + g.vhx;
+    c2 = bitrev(py, g.Ky) + (g.sy0 << g.Ky) + g.vhy;
+}
+
+__device__ __forceinline__ int skew_of(const ItemGeom& g, int p)
+{
+    return g.sx0 * (p & ((1 << g.Kx) - 1)) + g.sy0 * (p >> g.Kx);
+}
+
+// Buffer resource and byte offset of lane 0 for a column whose element dd is
+// at col[sd * dd], valid for dd in [0, E), addressed from displacement dd0.
+template <typename T>
+__device__ __forceinline__ void column_rsrc(const T* col, int sd, int E, int dd0, int lane,
+                                            __amdgpu_buffer_rsrc_t& rs, int& voff)
+{
+    if (sd > 0) {
+        rs = make_rsrc(col, E);
+        voff = 4 * (dd0 + lane);
+    } else {  // element dd at col - dd: the resource starts at dd = E - 1
+        rs = make_rsrc(col - (E - 1), E);
+        voff = 4 * (E - 1 - dd0 - lane);
+    }
+}
+
+// Buffer resource and lane-0 byte offset of the column that LDS slot p loads
+// for the tile at g.d0: block (px, py) at a skewed origin (forward) or slope
+// (bitrev px, bitrev py) at the common origin (adjoint).
+template <typename T>
+__device__ __forceinline__ void src_column(const DrtDesc* __restrict__ d, const ItemGeom& g, int slot, int p, int lane,
+                                           __amdgpu_buffer_rsrc_t& rs, int& voff, int& step)
+{
+    int c1, c2, dd0;
+    if (!g.adjoint) {
+        block_col(g, p, c1, c2);
+        dd0 = g.d0 - g.H - skew_of(g, p);
+    } else {
+        slope_col(g, p, c1, c2);
+        dd0 = g.d0;
+    }
+    if (d->src_mode == 0) {
+        const T* base = reinterpret_cast<const T*>(d->src) + d->phys[slot] * d->src_slot_stride;
+        column_rsrc(base + (((long long)c1 << g.n) + c2) * d->P_in, 1, d->E_in, dd0, lane, rs, voff);
+        step = 256;
+    } else {
+        const FrameMap f = d->fm[slot];
+        const T* base = reinterpret_cast<const T*>(d->vsrc[f.group]);
+        column_rsrc(base + ((long long)f.base + (long long)f.sx * c1 + (long long)f.sy * c2), f.sd, g.N, dd0, lane,
+                    rs, voff);
+        step = 256 * f.sd;
+    }
+}
+
+// Issues every global load of the wave's slots (p = wave + i * nwaves) for the
+// tile at g.d0: SPW * NCH loads in flight at once.
+template <typename T, int NCH, int SPW>
+__device__ __forceinline__ void load_regs(const DrtDesc* __restrict__ d, const ItemGeom& g, int slot, int wave,
+                                          int nwaves, int lane, uint32_t (&v)[SPW][NCH])
+{
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) {
+        __amdgpu_buffer_rsrc_t rs;
+        int voff, step;
+        src_column<T>(d, g, slot, wave + i * nwaves, lane, rs, voff, step);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) v[i][c] = bload(rs, voff + step * c);
+    }
+}
+
+template <typename T, int NCH, int SPW>
+__device__ __forceinline__ void regs_to_lds(const ItemGeom& g, T* lds, int wave, int nwaves, int lane,
+                                            const uint32_t (&v)[SPW][NCH])
+{
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) {
+        T* s = lds + slot_offset(wave + i * nwaves, g.Lp, g.pad) + lane;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) s[64 * c] = from_bits<T>(v[i][c]);
+    }
+}
+
+// Unpipelined load for shapes without a register buffer (NCH = 0 or many
+// slots per wave): per slot, all chunks in flight, then written to LDS.
+template <typename T, int NCH>
+__device__ __forceinline__ void load_direct(const DrtDesc* __restrict__ d, const ItemGeom& g, int slot, T* lds,
+                                            int wave, int nwaves, int lane)
+{
+    const int nch = NCH ? NCH : (g.L >> 6);
+    const int nslot = 1 << (g.Kx + g.Ky);
+    for (int p = wave; p < nslot; p += nwaves) {
+        __amdgpu_buffer_rsrc_t rs;
+        int voff, step;
+        src_column<T>(d, g, slot, p, lane, rs, voff, step);
+        T* s = lds + slot_offset(p, g.Lp, g.pad) + lane;
+        if (NCH) {
+            uint32_t v[NCH ? NCH : 1];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) v[c] = bload(rs, voff + step * c);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) s[64 * c] = from_bits<T>(v[c]);
+        } else {
+            for (int c = 0; c < nch; ++c) s[64 * c] = from_bits<T>(bload(rs, voff + step * c));
+        }
+    }
+}
+
+// Stores the tile at g.d0 of every slot. The destination column is one buffer
+// resource: writes outside [0, E) are dropped; positions past the tile width
+// (last chunk) are masked.
+template <typename T>
+__device__ __forceinline__ void store_tile(const DrtDesc* __restrict__ d, const ItemGeom& g, int slot, const T* lds,
+                                           int wave, int nwaves, int lane)
+{
+    const int nslot = 1 << (g.Kx + g.Ky);
+    const int q0 = g.adjoint ? 0 : g.H;
+    const int Eout = d->dst_mode == 0 ? d->E_out : g.N;
+    T* dstbase = d->dst_mode == 0 ? reinterpret_cast<T*>(d->dst) + d->phys[slot] * d->dst_slot_stride
+                                  : reinterpret_cast<T*>(d->vdst[d->fm[slot].group]);
+    const int accum = d->dst_mode == 1 && d->accum[slot];
+    const FrameMap f = d->fm[slot];
+    const int sdv = d->dst_mode == 0 ? 1 : f.sd;
+    const int step = 256 * sdv;
+    const int last = (g.T - 1) >> 6;  // chunk holding the tile's end
+    const bool last_live = 64 * last + lane < g.T;
+    for (int p = wave; p < nslot; p += nwaves) {
+        int c1, c2, dd0;
+        if (!g.adjoint) {  // common origin: positions H.. hold dd = d0..
+            slope_col(g, p, c1, c2);
+            dd0 = g.d0;
+        } else {           // child column (px, py) at its skewed origin
+            block_col(g, p, c1, c2);
+            dd0 = g.d0 - skew_of(g, p);
+        }
+        T* col = d->dst_mode == 0 ? dstbase + (((long long)c1 << g.n) + c2) * d->P_out
+                                  : dstbase + ((long long)f.base + (long long)f.sx * c1 + (long long)f.sy * c2);
+        __amdgpu_buffer_rsrc_t rs;
+        int voff;
+        column_rsrc(col, sdv, Eout, dd0, lane, rs, voff);
+        const T* s = lds + slot_offset(p, g.Lp, g.pad) + q0 + lane;
+        for (int c = 0; c <= last; ++c) {
+            if (c < last || last_live) {
+                T v = s[64 * c];
+                const int off = voff + step * c;
+                if (accum) v += from_bits<T>(bload(rs, off));
+                bstore(rs, off, to_bits(v));
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void zero_pads_fn(void* lds_raw, int elem_bytes, const ItemGeom& g, int wave, int nwaves,
+                                             int lane)
+{
+    uint32_t* lds = reinterpret_cast<uint32_t*>(lds_raw);
+    const int nslot = 1 << (g.Kx + g.Ky);
+    for (int p = wave; p <= nslot; p += nwaves)
+        if (lane < g.pad) lds[p * g.Lp + lane] = 0u;
+    (void)elem_bytes;
+}
+
+// All tiles of one work item (one column group of one slot). With a register
+// buffer (SPW > 0) the next tile's loads are issued before the current tile's
+// stages run, so global latency overlaps LDS work.
+template <typename T, int NCH, int SPW>
+__device__ __forceinline__ void process_group(const DrtDesc* __restrict__ d, ItemGeom& g, int slot, int ntiles,
+                                              T* lds, int wave, int nwaves, int lane)
+{
+    const int nch = NCH ? NCH : (g.L >> 6);
+    zero_pads_fn(lds, sizeof(T), g, wave, nwaves, lane);
+    if constexpr (SPW > 0) {
+        uint32_t v[SPW][NCH];
+        g.d0 = 0;
+        load_regs<T, NCH, SPW>(d, g, slot, wave, nwaves, lane, v);
+        for (int tile = 0; tile < ntiles; ++tile) {
+            g.d0 = tile * g.T;
+            regs_to_lds<T, NCH, SPW>(g, lds, wave, nwaves, lane, v);
+            __syncthreads();
+            if (tile + 1 < ntiles) {
+                ItemGeom gn = g;
+                gn.d0 = (tile + 1) * g.T;
+                load_regs<T, NCH, SPW>(d, gn, slot, wave, nwaves, lane, v);
+            }
+            run_stages<T, NCH>(lds, g.Lp, g.pad, nch, g.Kx, g.Ky, g.adjoint, wave, nwaves, lane);
+            store_tile<T>(d, g, slot, lds, wave, nwaves, lane);
+            __syncthreads();
+        }
+    } else {
+        for (int tile = 0; tile < ntiles; ++tile) {
+            g.d0 = tile * g.T;
+            load_direct<T, NCH>(d, g, slot, lds, wave, nwaves, lane);
+            __syncthreads();
+            run_stages<T, NCH>(lds, g.Lp, g.pad, nch, g.Kx, g.Ky, g.adjoint, wave, nwaves, lane);
+            store_tile<T>(d, g, slot, lds, wave, nwaves, lane);
+            __syncthreads();
+        }
+    }
+}
+
+// Register-buffer shape: SPW slots per wave, NCH chunks, at most 48 values.
+template <typename T, int NCH>
+__device__ __forceinline__ void dispatch_spw(const DrtDesc* __restrict__ d, ItemGeom& g, int slot, int ntiles, T* lds,
+                                             int wave, int nwaves, int lane)
+{
+    const int nslot = 1 << (g.Kx + g.Ky);
+    const int spw = (nslot % nwaves == 0) ? nslot / nwaves : 0;
+    if (NCH && spw == 8 && 8 * NCH <= 48) process_group<T, NCH, (NCH && 8 * NCH <= 48) ? 8 : 0>(d, g, slot, ntiles, lds, wave, nwaves, lane);
+    else if (NCH && spw == 4 && 4 * NCH <= 48) process_group<T, NCH, (NCH && 4 * NCH <= 48) ? 4 : 0>(d, g, slot, ntiles, lds, wave, nwaves, lane);
+    else if (NCH && spw == 2 && 2 * NCH <= 48) process_group<T, NCH, (NCH && 2 * NCH <= 48) ? 2 : 0>(d, g, slot, ntiles, lds, wave, nwaves, lane);
+    else if (NCH && spw == 1) process_group<T, NCH, NCH ? 1 : 0>(d, g, slot, ntiles, lds, wave, nwaves, lane);
+    else process_group<T, NCH, 0>(d, g, slot, ntiles, lds, wave, nwaves, lane);
 }
 
 template <typename T>
@@ -140,184 +466,44 @@ drt_pass_kernel(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwaves = blockDim.x >> 6;
 
+    // A work item is one column group of one dodecant slot; its work group
+    // walks the group's displacement tiles in order, so the cache lines that a
+    // tile boundary splits are completed in the same L2 and the halo a tile
+    // shares with the previous one is read from it.
     for (long long wg = blockIdx.x; wg < total_wg; wg += gridDim.x) {
         const DrtDesc* d = descs + find_desc_drt(descs, ndesc, wg);
-        const int ntiles = d->ntiles;
-        const int groups = d->groups_x * d->groups_y;
-        long long local = wg - d->wg_begin;
-        const int tile = (int)(local % ntiles);
-        local /= ntiles;
-        const int g = (int)(local % groups);
-        const int slot = (int)(local / groups);
+        const int local = (int)(wg - d->wg_begin);
+        const int lg_groups = (d->n - d->Kx) + (d->n - d->Ky);
+        const int gidx = local & ((1 << lg_groups) - 1);
+        const int slot = local >> lg_groups;
 
-        const int N = d->N, n = d->n;
-        const int Kx = d->Kx, Ky = d->Ky, mx0 = d->mx0, my0 = d->my0;
-        const int L = d->L, Lp = d->Lp, TT = d->T, H = d->H;
-        const int pad = Lp - L;
-        const int nch = L >> 6;
-        const int adjoint = d->adjoint;
-        const int gy = g & (d->groups_y - 1), gx = g >> (n - Ky);
-        const int sx0 = gx & ((1 << mx0) - 1);
-        const int vhx = (gx >> mx0) << (mx0 + Kx);
-        const int sy0 = gy & ((1 << my0) - 1);
-        const int vhy = (gy >> my0) << (my0 + Ky);
-        const int nslot = 1 << (Kx + Ky);
-        const int xmask = (1 << Kx) - 1;
-        const int d0 = tile * TT;
-        // adjoint outputs are skewed by up to smax: tiles past it hold nothing
-        if (adjoint && d0 >= d->E_out + sx0 * xmask + sy0 * ((1 << Ky) - 1)) continue;
+        ItemGeom g;
+        g.N = d->N; g.n = d->n;
+        g.Kx = d->Kx; g.Ky = d->Ky; g.mx0 = d->mx0; g.my0 = d->my0;
+        g.L = d->L; g.Lp = d->Lp; g.pad = g.Lp - g.L; g.T = d->T; g.H = d->H;
+        g.adjoint = d->adjoint;
+        g.d0 = 0;
+        const int gy = gidx & (d->groups_y - 1), gx = gidx >> (g.n - g.Ky);
+        g.sx0 = gx & ((1 << g.mx0) - 1);
+        g.vhx = (gx >> g.mx0) << (g.mx0 + g.Kx);
+        g.sy0 = gy & ((1 << g.my0) - 1);
+        g.vhy = (gy >> g.my0) << (g.my0 + g.Ky);
+        // adjoint outputs are skewed by up to smax: the group needs fewer tiles
+        const int span = g.adjoint ? d->E_out + g.sx0 * ((1 << g.Kx) - 1) + g.sy0 * ((1 << g.Ky) - 1) : d->E_out;
+        const int ntiles = min(d->ntiles, (span + g.T - 1) / g.T);
 
-        // zero pads (their positions depend on L, which varies across descriptors)
-        for (int i = threadIdx.x; i < (nslot + 1) * pad; i += blockDim.x) {
-            const int p = i / pad, o = i - p * pad;
-            lds[p * Lp + o] = zero_of<T>();
+        switch (g.L >> 6) {
+            case 1: dispatch_spw<T, 1>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+            case 2: dispatch_spw<T, 2>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+            case 3: dispatch_spw<T, 3>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+            case 4: dispatch_spw<T, 4>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+            case 5: dispatch_spw<T, 5>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+            case 6: dispatch_spw<T, 6>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+            default: dispatch_spw<T, 0>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
         }
-
-        // ---------------- load ----------------
-        // slot p holds the column of block (px, py) (forward, skewed origin)
-        // or of slope (bitrev px, bitrev py) (adjoint, common origin).
-        const T* srcbase = d->src_mode == 0 ? reinterpret_cast<const T*>(d->src) + d->phys[slot] * d->src_slot_stride
-                                            : reinterpret_cast<const T*>(d->vsrc[d->fm[slot].group]);
-        const int Ein = d->src_mode == 0 ? d->E_in : N;
-        {
-            constexpr int G = 2, CB = 8;
-            for (int p0 = wave; p0 < nslot; p0 += G * nwaves) {
-                const T* col[G];
-                int sdv[G], dd0v[G];
-                bool live[G];
-#pragma unroll
-                for (int gq = 0; gq < G; ++gq) {
-                    const int p = p0 + gq * nwaves;
-                    live[gq] = p < nslot;
-                    const int px = p & xmask, py = p >> Kx;
-                    int c1, c2;
-                    if (!adjoint) {
-                        c1 = sx0 + (px << mx0) + vhx;
-                        c2 = sy0 + (py << my0) + vhy;
-                        dd0v[gq] = d0 - H - sx0 * px - sy0 * py;
-                    } else {
-                        c1 = bitrev(px, Kx) + (sx0 << Kx) + vhx;
-                        c2 = bitrev(py, Ky) + (sy0 << Ky) + vhy;
-                        dd0v[gq] = d0;
-                    }
-                    if (d->src_mode == 0) {
-                        col[gq] = srcbase + (((long long)c1 << n) + c2) * d->P_in;
-                        sdv[gq] = 1;
-                    } else {
-                        const FrameMap f = d->fm[slot];
-                        col[gq] = srcbase + ((long long)f.base + (long long)f.sx * c1 + (long long)f.sy * c2);
-                        sdv[gq] = f.sd;
-                    }
-                }
-                for (int cb = 0; cb < nch; cb += CB) {
-                    T v[G][CB];
-#pragma unroll
-                    for (int gq = 0; gq < G; ++gq)
-#pragma unroll
-                        for (int c = 0; c < CB; ++c) {
-                            const int l = 64 * (cb + c) + lane;
-                            const int dd = dd0v[gq] + l;
-                            v[gq][c] = (live[gq] && cb + c < nch && dd >= 0 && dd < Ein) ? col[gq][sdv[gq] * dd]
-                                                                                       : zero_of<T>();
-                        }
-#pragma unroll
-                    for (int gq = 0; gq < G; ++gq) {
-                        T* s = lds + slot_offset(p0 + gq * nwaves, Lp, pad);
-#pragma unroll
-                        for (int c = 0; c < CB; ++c)
-                            if (live[gq] && cb + c < nch) s[64 * (cb + c) + lane] = v[gq][c];
-                    }
-                }
-            }
-        }
-        __syncthreads();
-
-        // ---------------- stages ----------------
-        // x-stage j and y-stage j run together as one radix-4 step while both
-        // axes have them; the rest run as radix-2 steps. Each axis keeps its
-        // stage order, which is all the in-place slot convention needs.
-        const int kmax = Kx > Ky ? Kx : Ky;
-        for (int jj = 0; jj < kmax; ++jj) {
-            const int j = adjoint ? kmax - 1 - jj : jj;
-            const bool hx = j < Kx, hy = j < Ky;
-            const int bx = 1 << j, by = 1 << (Kx + j);
-            if (hx && hy) {
-                const int nq = nslot >> 2;
-                for (int q = wave; q < nq; q += nwaves) {
-                    // insert zero bits at positions j (x) and Kx + j (y)
-                    int p = q;
-                    p = ((p >> j) << (j + 1)) | (p & (bx - 1));
-                    p = ((p >> (Kx + j)) << (Kx + j + 1)) | (p & (by - 1));
-                    const int tx = bitrev(p & (bx - 1), j);
-                    const int ty = bitrev((p >> Kx) & (bx - 1), j);
-                    T* s00 = lds + slot_offset(p, Lp, pad);
-                    T* s10 = lds + slot_offset(p + bx, Lp, pad);
-                    T* s01 = lds + slot_offset(p + by, Lp, pad);
-                    T* s11 = lds + slot_offset(p + bx + by, Lp, pad);
-                    if (!adjoint) step4_fwd(s00, s10, s01, s11, nch, tx, ty, lane);
-                    else step4_adj(s00, s10, s01, s11, nch, tx, ty, lane);
-                }
-            } else {
-                const int bit = hx ? j : Kx + j;
-                const int h = 1 << bit;
-                const int np = nslot >> 1;
-                for (int q = wave; q < np; q += nwaves) {
-                    const int p = ((q >> bit) << (bit + 1)) | (q & (h - 1));
-                    const int axis_bits = hx ? (p & xmask) : (p >> Kx);
-                    const int t = bitrev(axis_bits & ((1 << j) - 1), j);
-                    T* s0 = lds + slot_offset(p, Lp, pad);
-                    if (!adjoint) step2_fwd(s0, s0 + h * Lp, nch, t, lane);
-                    else step2_adj(s0, s0 + h * Lp, nch, t, lane);
-                }
-            }
-            __syncthreads();
-        }
-
-        // ---------------- store ----------------
-        {
-            const int q0 = adjoint ? 0 : H;
-            const int Eout = d->dst_mode == 0 ? d->E_out : N;
-            T* dstbase = d->dst_mode == 0 ? reinterpret_cast<T*>(d->dst) + d->phys[slot] * d->dst_slot_stride
-                                          : reinterpret_cast<T*>(d->vdst[d->fm[slot].group]);
-            const int accum = d->dst_mode == 1 && d->accum[slot];
-            const int nt = d->nt_store;
-            for (int p = wave; p < nslot; p += nwaves) {
-                const int px = p & xmask, py = p >> Kx;
-                int c1, c2, dd0;
-                if (!adjoint) {  // common origin: positions H.. hold dd = d0..
-                    c1 = bitrev(px, Kx) + (sx0 << Kx) + vhx;
-                    c2 = bitrev(py, Ky) + (sy0 << Ky) + vhy;
-                    dd0 = d0;
-                } else {         // child column (px, py) at its skewed origin
-                    c1 = sx0 + (px << mx0) + vhx;
-                    c2 = sy0 + (py << my0) + vhy;
-                    dd0 = d0 - sx0 * px - sy0 * py;
-                }
-                T* col;
-                int sd;
-                if (d->dst_mode == 0) {
-                    col = dstbase + (((long long)c1 << n) + c2) * d->P_out;
-                    sd = 1;
-                } else {
-                    const FrameMap f = d->fm[slot];
-                    col = dstbase + ((long long)f.base + (long long)f.sx * c1 + (long long)f.sy * c2);
-                    sd = f.sd;
-                }
-                const T* s = lds + slot_offset(p, Lp, pad) + q0;
-                const int qlo = max(0, -dd0), qhi = min(TT, Eout - dd0);
-                for (int q = qlo + lane; q < qhi; q += 64) {
-                    T* dst = col + sd * (dd0 + q);
-                    T v = s[q];
-                    if (accum) v += *dst;
-                    if (nt) __builtin_nontemporal_store(v, dst);
-                    else *dst = v;
-                }
-            }
-        }
-        __syncthreads();
     }
 }
 

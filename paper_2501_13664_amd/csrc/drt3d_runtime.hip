@@ -427,7 +427,7 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
             if (s->kind == S_DRT) {
                 for (DrtDesc d : s->drt) {
                     d.wg_begin = wg;
-                    wg += (long long)d.nslots * d.groups_x * d.groups_y * d.ntiles;
+                    wg += (long long)d.nslots * d.groups_x * d.groups_y;
                     prog.drt.push_back(d);
                 }
             } else {
