@@ -397,6 +397,67 @@ __device__ __forceinline__ void store_tile(const DrtDesc* __restrict__ d, const 
     }
 }
 
+// Line-aligned store of the tile at g.d0 for the wave's slots. HBM writes are
+// cheapest as whole 128-byte lines, and a column's tile rarely starts or ends
+// on one, so each tile writes only the lines it completes: elements from the
+// last line boundary the previous tile reached (kept in `carry`, at most 31
+// of them) up to the last line boundary inside this tile, or to the column
+// end on the last tile. The tail goes into `carry` for the next tile. Lines
+// split between two columns at a column start stay partial. Needs T >= 32.
+template <typename T, int SPW>
+__device__ __forceinline__ void store_tile_aligned(const DrtDesc* __restrict__ d, const ItemGeom& g, int slot,
+                                                   const T* lds, int wave, int nwaves, int lane, bool last_tile,
+                                                   uint32_t (&carry)[SPW])
+{
+    const int q0 = g.adjoint ? 0 : g.H;
+    const int Eout = d->dst_mode == 0 ? d->E_out : g.N;
+    T* dstbase = d->dst_mode == 0 ? reinterpret_cast<T*>(d->dst) + d->phys[slot] * d->dst_slot_stride
+                                  : reinterpret_cast<T*>(d->vdst[d->fm[slot].group]);
+    const int accum = d->dst_mode == 1 && d->accum[slot];
+    const FrameMap f = d->fm[slot];
+    const int sdv = d->dst_mode == 0 ? 1 : f.sd;
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) {
+        const int p = wave + i * nwaves;
+        int c1, c2, dd0;
+        if (!g.adjoint) {  // common origin: positions H.. hold dd = d0..
+            slope_col(g, p, c1, c2);
+            dd0 = g.d0;
+        } else {           // child column (px, py) at its skewed origin
+            block_col(g, p, c1, c2);
+            dd0 = g.d0 - skew_of(g, p);
+        }
+        const long long cofs = d->dst_mode == 0 ? (((long long)c1 << g.n) + c2) * d->P_out
+                                                : (long long)f.base + (long long)f.sx * c1 + (long long)f.sy * c2;
+        // element index of displacement dd is cofs + sdv * dd; a line boundary
+        // at dd means that index (for sdv = -1: index + 1) is a multiple of 32.
+        const int mis = sdv > 0 ? (int)(cofs & 31) : (int)((cofs + 1) & 31);
+        auto line_floor = [&](int x) { return sdv > 0 ? x - ((mis + x) & 31) : x - ((x - mis) & 31); };
+        const int fbeg = dd0 <= 0 ? dd0 : line_floor(dd0);   // first dd written now
+        const int fend = last_tile ? dd0 + g.T : line_floor(dd0 + g.T);
+        __amdgpu_buffer_rsrc_t rs;
+        int voff;
+        column_rsrc(dstbase + cofs, sdv, Eout, fbeg, lane, rs, voff);
+        const T* s = lds + slot_offset(p, g.Lp, g.pad) + q0 - dd0;  // s[dd] holds displacement dd
+        const int cnt = fend - fbeg;
+        for (int c = 0; 64 * c < cnt; ++c) {
+            const int k = 64 * c + lane;
+            if (k < cnt) {
+                const int dd = fbeg + k;
+                T v = dd < dd0 ? from_bits<T>(carry[i]) : s[dd];
+                const int off = voff + 256 * sdv * c;
+                if (accum) v += from_bits<T>(bload(rs, off));
+                bstore(rs, off, to_bits(v));
+            }
+        }
+        // tail [fend, dd0 + T) for the next tile: lane k holds dd = fend + k
+        if (!last_tile) {
+            const int tail = dd0 + g.T - fend;
+            carry[i] = lane < tail ? to_bits(s[fend + lane]) : 0u;
+        }
+    }
+}
+
 __device__ __forceinline__ void zero_pads_fn(void* lds_raw, int elem_bytes, const ItemGeom& g, int wave, int nwaves,
                                              int lane)
 {
@@ -418,6 +479,9 @@ __device__ __forceinline__ void process_group(const DrtDesc* __restrict__ d, Ite
     zero_pads_fn(lds, sizeof(T), g, wave, nwaves, lane);
     if constexpr (SPW > 0) {
         uint32_t v[SPW][NCH];
+        uint32_t carry[SPW];
+#pragma unroll
+        for (int i = 0; i < SPW; ++i) carry[i] = 0u;
         g.d0 = 0;
         load_regs<T, NCH, SPW>(d, g, slot, wave, nwaves, lane, v);
         for (int tile = 0; tile < ntiles; ++tile) {
@@ -430,7 +494,7 @@ __device__ __forceinline__ void process_group(const DrtDesc* __restrict__ d, Ite
                 load_regs<T, NCH, SPW>(d, gn, slot, wave, nwaves, lane, v);
             }
             run_stages<T, NCH>(lds, g.Lp, g.pad, nch, g.Kx, g.Ky, g.adjoint, wave, nwaves, lane);
-            store_tile<T>(d, g, slot, lds, wave, nwaves, lane);
+            store_tile_aligned<T, SPW>(d, g, slot, lds, wave, nwaves, lane, tile + 1 == ntiles, carry);
             __syncthreads();
         }
     } else {
@@ -506,6 +570,171 @@ drt_pass_kernel(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg
         }
     }
 }
+
+// ---------------------------------------------------------------------------
+// Shape-specialised pass kernel: KX x-stages, KY y-stages (KX, KY <= 3,
+// 2^(KX+KY) >= 8 columns), L = 64 * NCH, eight wavefronts. Wave w owns the
+// slots p = w + 8 i, which share the x index px = w mod 2^KX, so a slot's
+// column offset is a per-wave base plus a per-slot stride. Each side of the
+// pass (source, destination) is one buffer resource over its whole region (a
+// stage buffer slot, one dodecant of the output, or the volume; regions below
+// 2^31 bytes); column offsets travel in VGPRs, so the hardware range check
+// covers the full offset, and each column's own range [0, E) is enforced in
+// the lanes: out-of-range loads are replaced by zero, out-of-range stores are
+// masked.
+namespace fast {
+
+constexpr int NW = 8;
+
+template <int KX>
+__device__ __forceinline__ int py_of(int wave, int i) { return (wave >> KX) + i * (NW >> KX); }
+
+template <typename T, int KX, int KY, int NCH>
+__global__ void __launch_bounds__(512)
+drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
+{
+    constexpr int NS = 1 << (KX + KY), SPW = NS / NW, L = 64 * NCH;
+    static_assert(NS >= 8 && KX <= 3 && KY <= 3, "shape");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int px = wave & ((1 << KX) - 1);
+    const int rpx = bitrev(px, KX);
+
+    for (long long wg = blockIdx.x; wg < total_wg; wg += gridDim.x) {
+        const DrtDesc* d = descs + find_desc_drt(descs, ndesc, wg);
+        const int local = (int)(wg - d->wg_begin);
+        const int n = d->n, N = d->N, mx0 = d->mx0, my0 = d->my0;
+        const int lg_groups = (n - KX) + (n - KY);
+        const int gidx = local & ((1 << lg_groups) - 1);
+        const int slot = local >> lg_groups;
+        const int T_ = d->T, H = d->H, Lp = d->Lp, pad = Lp - L, adjoint = d->adjoint;
+        const int gy = gidx & ((1 << (n - KY)) - 1), gx = gidx >> (n - KY);
+        const int sx0 = gx & ((1 << mx0) - 1);
+        const int vhx = (gx >> mx0) << (mx0 + KX);
+        const int sy0 = gy & ((1 << my0) - 1);
+        const int vhy = (gy >> my0) << (my0 + KY);
+        const int span = adjoint ? d->E_out + sx0 * ((1 << KX) - 1) + sy0 * ((1 << KY) - 1) : d->E_out;
+        const int ntiles = min(d->ntiles, (span + T_ - 1) / T_);
+        const FrameMap fm = d->fm[slot];
+
+        // block column (px, py): c1 = sx0 + (px << mx0) + vhx, c2 = sy0 + (py << my0) + vhy
+        // slope column:          c1 = bitrev(px) + (sx0 << KX) + vhx, c2 = bitrev(py) + (sy0 << KY) + vhy
+        const int c1b = sx0 + (px << mx0) + vhx, c2b = sy0 + vhy;
+        const int c1s = rpx + (sx0 << KX) + vhx, c2s = (sy0 << KY) + vhy;
+        // source: element of slot i at displacement dd is region[o + y(i)*ys + sd*dd]
+        __amdgpu_buffer_rsrc_t rs_src, rs_dst;
+        int so, sys, ssd, sE, do_, dys, dsd, dE;
+        if (d->src_mode == 0) {
+            const T* base = reinterpret_cast<const T*>(d->src) + d->phys[slot] * d->src_slot_stride;
+            rs_src = make_rsrc(base, (int)d->src_slot_stride);
+            const int c1 = adjoint ? c1s : c1b, c2 = adjoint ? c2s : c2b;
+            so = ((c1 << n) + c2) * d->P_in;
+            sys = adjoint ? d->P_in : (d->P_in << my0);
+            ssd = 1;
+            sE = d->E_in;
+        } else {
+            rs_src = make_rsrc(reinterpret_cast<const T*>(d->vsrc[fm.group]), N * N * N);
+            so = fm.base + fm.sx * c1b + fm.sy * c2b;
+            sys = fm.sy * (1 << my0);
+            ssd = fm.sd;
+            sE = N;
+        }
+        if (d->dst_mode == 0) {
+            T* base = reinterpret_cast<T*>(d->dst) + d->phys[slot] * d->dst_slot_stride;
+            rs_dst = make_rsrc(base, (int)d->dst_slot_stride);
+            const int c1 = adjoint ? c1b : c1s, c2 = adjoint ? c2b : c2s;
+            do_ = ((c1 << n) + c2) * d->P_out;
+            dys = adjoint ? (d->P_out << my0) : d->P_out;
+            dsd = 1;
+            dE = d->E_out;
+        } else {
+            rs_dst = make_rsrc(reinterpret_cast<T*>(d->vdst[fm.group]), N * N * N);
+            do_ = fm.base + fm.sx * c1b + fm.sy * c2b;
+            dys = fm.sy * (1 << my0);
+            dsd = fm.sd;
+            dE = N;
+        }
+        const int accum = d->dst_mode == 1 && d->accum[slot];
+        const int q0 = adjoint ? 0 : H;
+
+        // zero pads
+        for (int p = wave; p <= NS; p += NW)
+            if (lane < pad) lds[p * Lp + lane] = zero_of<T>();
+
+        uint32_t v[SPW][NCH];
+        uint32_t carry[SPW];
+#pragma unroll
+        for (int i = 0; i < SPW; ++i) carry[i] = 0u;
+
+        auto issue_loads = [&](int d0) {
+#pragma unroll
+            for (int i = 0; i < SPW; ++i) {
+                const int py = py_of<KX>(wave, i);
+                const int y = adjoint ? bitrev(py, KY) : py;
+                const int dd0 = adjoint ? d0 : d0 - H - sx0 * px - sy0 * py;
+                const int colo = so + y * sys;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    // lanes outside the column get an offset past the resource:
+                    // the hardware returns 0 for them without touching memory
+                    const int dd = dd0 + 64 * c + lane;
+                    const bool in = (unsigned)dd < (unsigned)sE;
+                    v[i][c] = bload(rs_src, in ? 4 * (colo + ssd * dd) : -1);
+                }
+            }
+        };
+
+        issue_loads(0);
+        for (int tile = 0; tile < ntiles; ++tile) {
+            const int d0 = tile * T_;
+#pragma unroll
+            for (int i = 0; i < SPW; ++i) {
+                T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + lane;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) sl[64 * c] = from_bits<T>(v[i][c]);
+            }
+            __syncthreads();
+            if (tile + 1 < ntiles) issue_loads(d0 + T_);
+            run_stages<T, NCH>(lds, Lp, pad, NCH, KX, KY, adjoint, wave, NW, lane);
+
+            // line-aligned store with carry (see store_tile_aligned)
+            const bool last_tile = tile + 1 == ntiles;
+#pragma unroll
+            for (int i = 0; i < SPW; ++i) {
+                const int py = py_of<KX>(wave, i);
+                const int y = adjoint ? py : bitrev(py, KY);
+                const int dd0 = adjoint ? d0 - sx0 * px - sy0 * py : d0;
+                const int colo = do_ + y * dys;
+                const int mis = dsd > 0 ? (colo & 31) : ((colo + 1) & 31);
+                auto line_floor = [&](int x) { return dsd > 0 ? x - ((mis + x) & 31) : x - ((x - mis) & 31); };
+                const int fbeg = dd0 <= 0 ? dd0 : line_floor(dd0);
+                const int fend = last_tile ? dd0 + T_ : line_floor(dd0 + T_);
+                const T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + q0 - dd0;
+                const int cnt = fend - fbeg;
+#pragma unroll
+                for (int c = 0; c < NCH + 1; ++c) {
+                    const int k = 64 * c + lane;
+                    const int dd = fbeg + k;
+                    if (k < cnt && (unsigned)dd < (unsigned)dE) {
+                        T val = dd < dd0 ? from_bits<T>(carry[i]) : sl[dd];
+                        const int off = 4 * (colo + dsd * dd);
+                        if (accum) val += from_bits<T>(bload(rs_dst, off));
+                        bstore(rs_dst, off, to_bits(val));
+                    }
+                }
+                if (!last_tile) {
+                    const int tail = dd0 + T_ - fend;
+                    carry[i] = lane < tail ? to_bits(sl[fend + lane]) : 0u;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+}  // namespace fast
 
 // ---------------------------------------------------------------------------
 // out[b][c][r] (+)= in[b][r][c]; 64 x 64 tiles through LDS, 256 threads.
@@ -625,13 +854,58 @@ djt_stage_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_w
 }
 
 // ---------------------------------------------------------------------------
+template <typename T>
+static const void* fast_kernel(int kx, int ky, int nch)
+{
+#define DRT3D_FAST(KX, KY, NC) \
+    if (kx == KX && ky == KY && nch == NC) return reinterpret_cast<const void*>(&fast::drt_pass_fast<T, KX, KY, NC>);
+#define DRT3D_FAST_NCH(KX, KY) \
+    DRT3D_FAST(KX, KY, 1) DRT3D_FAST(KX, KY, 2) DRT3D_FAST(KX, KY, 3) DRT3D_FAST(KX, KY, 4) \
+    DRT3D_FAST(KX, KY, 5) DRT3D_FAST(KX, KY, 6)
+    DRT3D_FAST_NCH(3, 3)
+    DRT3D_FAST_NCH(2, 2)
+    DRT3D_FAST_NCH(3, 2)
+    DRT3D_FAST_NCH(2, 3)
+#undef DRT3D_FAST_NCH
+#undef DRT3D_FAST
+    return nullptr;
+}
+
+template <typename T>
+static hipError_t set_fast_lds_limit(size_t bytes)
+{
+    const int shapes[4][2] = {{3, 3}, {2, 2}, {3, 2}, {2, 3}};
+    for (auto& sh : shapes)
+        for (int nc = 1; nc <= 6; ++nc) {
+            hipError_t e = hipFuncSetAttribute(fast_kernel<T>(sh[0], sh[1], nc),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e != hipSuccess) return e;
+        }
+    return hipSuccess;
+}
+
 hipError_t set_drt_lds_limit(int is_float, size_t bytes)
 {
+    {
+        hipError_t e = is_float ? set_fast_lds_limit<float>(bytes) : set_fast_lds_limit<uint32_t>(bytes);
+        if (e != hipSuccess) return e;
+    }
     if (is_float)
         return hipFuncSetAttribute(reinterpret_cast<const void*>(&drt_pass_kernel<float>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&drt_pass_kernel<uint32_t>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+int drt_fast_available(int kx, int ky, int nch) { return fast_kernel<uint32_t>(kx, ky, nch) != nullptr; }
+
+hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, const DrtDesc* d_descs, int ndesc,
+                           long long total_wg, int grid, size_t lds_bytes, hipStream_t s)
+{
+    const void* k = is_float ? fast_kernel<float>(kx, ky, nch) : fast_kernel<uint32_t>(kx, ky, nch);
+    if (!k) return hipErrorInvalidValue;
+    void* args[] = {&d_descs, &ndesc, &total_wg};
+    return hipLaunchKernel(k, dim3(grid), dim3(512), args, lds_bytes, s);
 }
 
 hipError_t launch_drt_pass(int is_float, const DrtDesc* d_descs, int ndesc, long long total_wg,

@@ -67,5 +67,9 @@ hipError_t launch_djt_stage(int is_float, const DjtDesc* d_descs, int ndesc, lon
 hipError_t launch_transpose(int is_float, const void* in, void* out, int R, int C, int batches,
                             int add, hipStream_t s);
 hipError_t set_drt_lds_limit(int is_float, size_t bytes);
+// Shape-specialised DRT pass kernels (eight wavefronts per work group).
+int drt_fast_available(int kx, int ky, int nch);
+hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, const DrtDesc* d_descs, int ndesc,
+                           long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
 
 }  // namespace drt3d

@@ -78,6 +78,7 @@ static int popcount12(uint32_t mask)
 }
 
 static inline long long round4(long long x) { return (x + 3) & ~3LL; }
+static inline long long round32(long long x) { return (x + 31) & ~31LL; }
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // ------------------------------------------------------------------ frames
@@ -352,6 +353,7 @@ struct Step {
     std::vector<DrtDesc> drt;
     std::vector<DjtDesc> djt;
     int waves = 4;     // wavefronts per work group
+    int shape = 0;     // DRT: Kx | Ky << 4 | (L / 64) << 8 (launches merge only equal shapes)
     size_t lds = 0;    // dynamic LDS bytes
     double bytes = 0;  // algorithmic bytes (reads of inputs + writes of outputs)
     // transpose: out[b][c][r] (+)= in[b][r][c]
@@ -363,6 +365,7 @@ struct Step {
 struct Launch {
     int kind;
     std::string name;
+    int fast_kx = -1, fast_ky = -1, fast_nch = -1;  // shape-specialised DRT kernel, if any
     int first = 0, ndesc = 0;
     long long total_wg = 0;
     int block = 64;
@@ -403,7 +406,9 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
         const Step* s0 = order[i];
         size_t j = i + 1;
         if (merge && s0->kind != S_TRANSPOSE)
-            while (j < order.size() && order[j]->key == s0->key && order[j]->kind == s0->kind) ++j;
+            while (j < order.size() && order[j]->key == s0->key && order[j]->kind == s0->kind &&
+                   order[j]->shape == s0->shape)
+                ++j;
         Launch L;
         L.kind = s0->kind;
         L.name = s0->name;
@@ -443,6 +448,22 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
         L.block = 64 * waves;
         L.lds = lds;
         L.bytes = bytes;
+        if (s0->kind == S_DRT && L.block == 512) {
+            // one shape across the launch's descriptors -> specialised kernel
+            const DrtDesc& f = prog.drt[L.first];
+            bool same = true;
+            for (int q = L.first; q < L.first + L.ndesc; ++q) {
+                const DrtDesc& e = prog.drt[q];
+                // the specialised kernel addresses each region with 32-bit
+                // byte offsets: N <= 512 keeps every region below 2^31 bytes
+                same = same && e.Kx == f.Kx && e.Ky == f.Ky && e.L == f.L && e.N <= 512;
+            }
+            if (same && (f.L & 63) == 0 && drt_fast_available(f.Kx, f.Ky, f.L >> 6)) {
+                L.fast_kx = f.Kx;
+                L.fast_ky = f.Ky;
+                L.fast_nch = f.L >> 6;
+            }
+        }
         prog.launches.push_back(L);
         i = j;
     }
@@ -511,8 +532,12 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
             if (L.lds > (size_t)di.max_lds)
                 return fail(DRT3D_EINVAL, "%s needs %zu bytes of LDS, the device allows %d", L.name.c_str(), L.lds,
                             di.max_lds);
-            e = launch_drt_pass(p.is_float, d_drt + L.first, L.ndesc, L.total_wg, L.block,
-                                grid_for(L.total_wg, di, p.persistent), L.lds, s);
+            if (L.fast_kx >= 0)
+                e = launch_drt_fast(p.is_float, L.fast_kx, L.fast_ky, L.fast_nch, d_drt + L.first, L.ndesc,
+                                    L.total_wg, grid_for(L.total_wg, di, p.persistent), L.lds, s);
+            else
+                e = launch_drt_pass(p.is_float, d_drt + L.first, L.ndesc, L.total_wg, L.block,
+                                    grid_for(L.total_wg, di, p.persistent), L.lds, s);
         } else if (L.kind == S_DJT) {
             e = launch_djt_stage(p.is_float, d_djt + L.first, L.ndesc, L.total_wg, L.block,
                                  grid_for(L.total_wg, di, p.persistent), s);
@@ -561,7 +586,9 @@ static long long max_intermediate_extent(int N)
     return 2LL * N + (1LL << (n - 1)) - 2;  // all of one axis, all but one stage of the other
 }
 
-static long long drt_stage_elems_per_dod(int N) { return (long long)N * N * round4(max_intermediate_extent(N)); }
+// Intermediate columns are padded to 32 elements so that each starts on a
+// 128-byte line.
+static long long drt_stage_elems_per_dod(int N) { return (long long)N * N * round32(max_intermediate_extent(N)); }
 
 static const long long kStageBudget = 8LL << 30;  // stage-buffer bytes of one single-volume call
 
@@ -597,7 +624,7 @@ static bool choose_tiles(const PassGeom& g, int adjoint, int lds_elems, int& T, 
     const int skew = adjoint ? ((1 << g.mx0) - 1) * ((1 << g.Kx) - 1) + ((1 << g.my0) - 1) * ((1 << g.Ky) - 1) : 0;
     const int span = E + skew;
     const int Lmax = (int)(((lds_elems - pad) / ns - pad) & ~63LL);
-    if (Lmax - H < 16) return false;
+    if (Lmax - H < 32) return false;  // tiles of at least one 128-byte line
     ntiles = (span + (Lmax - H) - 1) / (Lmax - H);
     const int Tmin = (span + ntiles - 1) / ntiles;
     L = (Tmin + H + 63) & ~63;
@@ -710,7 +737,7 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             } else {
                 d.src = S[(step - 1) & 1];
                 d.src_slot_stride = per;
-                d.P_in = (int)round4(d.E_in);
+                d.P_in = (int)round32(d.E_in);
             }
             if (last && !adjoint) {
                 d.dst = (char*)io.out + (size_t)c0 * slot_out * elem;
@@ -723,7 +750,7 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             } else {
                 d.dst = S[step & 1];
                 d.dst_slot_stride = per;
-                d.P_out = (int)round4(d.E_out);
+                d.P_out = (int)round32(d.E_out);
             }
             const int K = g.Kx + g.Ky;
             const int waves = std::min(t.waves, std::max(1, 1 << (K - 1)));
@@ -731,9 +758,10 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             const double cols = (double)N * N;
             char nm[32];
             snprintf(nm, sizeof nm, "drt_%s_p%d", adjoint ? "adj" : "fwd", pi + 1);
+            const int shape = g.Kx | (g.Ky << 4) | ((L >> 6) << 8);
             if (!(last && adjoint)) {
                 Step s; s.kind = S_DRT; s.key = kKeyPass + step; s.name = nm;
-                s.waves = waves; s.lds = lds;
+                s.waves = waves; s.lds = lds; s.shape = shape;
                 s.bytes = (double)ns * cols * elem * (first && !adjoint ? N + d.E_out : d.E_in + d.E_out);
                 s.drt.push_back(d);
                 steps.push_back(s);
@@ -759,7 +787,7 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
                     }
                     e.nslots = k;
                     Step s; s.kind = S_DRT; s.key = kKeyRound + r; s.name = nm;
-                    s.waves = waves; s.lds = lds;
+                    s.waves = waves; s.lds = lds; s.shape = shape;
                     double acc_reads = 0;
                     for (int q = 0; q < k; ++q) acc_reads += e.accum[q] ? (double)N : 0.0;
                     s.bytes = cols * elem * ((double)k * (d.E_in + d.E_out) + acc_reads);
@@ -883,8 +911,9 @@ static std::string program_signature(const Program& p, void* d_area)
     snprintf(buf, sizeof buf, "%p|%d|", d_area, p.is_float);
     sig += buf;
     for (const Launch& L : p.launches) {
-        snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%zu:%p:%p:%d:%d:%d:%d;", L.kind, L.first, L.ndesc, L.total_wg,
-                 L.block, L.lds, L.t_in, L.t_out, L.t_R, L.t_C, L.t_batches, L.t_add);
+        snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%zu:%p:%p:%d:%d:%d:%d:%d.%d.%d;", L.kind, L.first, L.ndesc,
+                 L.total_wg, L.block, L.lds, L.t_in, L.t_out, L.t_R, L.t_C, L.t_batches, L.t_add, L.fast_kx,
+                 L.fast_ky, L.fast_nch);
         sig += buf;
     }
     return sig;
