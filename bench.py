@@ -10,8 +10,19 @@ U = 12 * log2(N) * N^2 * 3N (Algorithm 1's writes per stage, summed over the
 stages and dodecants). `roofline` covers the dominant kernel, timed with HIP
 events recorded on the launch stream around every launch of the timed
 region; its algorithmic bytes are the reads of each pass's input extent plus
-the writes of its output extent. `cpu_baseline` times the oracle's naive
-Algorithm 1 on one dodecant of the same cube (scaled to the job).
+the writes of its output extent; `traffic` is the HBM bytes per launch from
+the committed rocprofv3 counter summary when it was taken on the current
+sources. `cpu_baseline` times the oracle's naive Algorithm 1 on one dodecant of
+the same cube (scaled to the job).
+
+Two further measurements ride along (skipped with --no-batched / --no-diff):
+the batched forward of 96 float32 cubes of mixed N against per-volume calls,
+and the differentiable transform (forward + backward through autograd) of a
+batch of 8 float32 N=128 cubes against per-volume forward + adjoint calls;
+both check that the two ways give bit-identical results.
+
+--copy-calibration runs only a plain 1 GiB device-to-device copy (five times),
+the reference kernel that scales the HBM byte counters.
 """
 import argparse
 import json
@@ -32,19 +43,29 @@ def updates(N, ndod=12):
     return ndod * n * N * N * 3 * N
 
 
+SOURCES = ["paper_2501_13664_amd/csrc/drt3d_device.hip", "paper_2501_13664_amd/csrc/drt3d_runtime.hip",
+           "paper_2501_13664_amd/csrc/drt3d_internal.h"]
+
+
+def sources_sha256():
+    """One hash over the HIP sources (kernels and the launch planning)."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in SOURCES:
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()
+
+
 def _traffic_record(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+    summary, if it was taken on the current sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    import hashlib
-    src = os.path.join(ROOT, "paper_2501_13664_amd", "csrc", "drt3d_device.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
     ent = rec.get(kernel)
-    if not ent or ent.get("source_sha256") != h:
+    if not ent or ent.get("sources_sha256") != sources_sha256():
         return None
     return ent.get("bytes_per_launch")
 
@@ -65,37 +86,88 @@ def cpu_baseline(vol):
     }
 
 
+def _best_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return best * 1e3
+
+
 def batched_speedup(api, torch, reps=5):
-    """96 float32 cubes of mixed N: one batched call vs per-volume calls."""
+    """96 float32 cubes of mixed N (48 x 32^3, 32 x 64^3, 12 x 128^3, 4 x 256^3):
+    one batched call vs per-volume calls on the same stream."""
     import workloads
     cubes = [torch.from_numpy(c).cuda() for c in workloads.mixed_batch()]
     outs = [torch.empty(api.drt3d_out_shape(c.shape[0]), dtype=torch.float32, device="cuda") for c in cubes]
-    ws_b = None
-    api.drt3d_forward_batched(cubes, outs=outs)
-    torch.cuda.synchronize()
 
     def per_volume():
         for c, o in zip(cubes, outs):
             api.drt3d_forward(c, out=o)
 
     def batched():
-        api.drt3d_forward_batched(cubes, outs=outs, workspace=ws_b)
+        api.drt3d_forward_batched(cubes, outs=outs)
 
-    res = {}
-    for name, fn in (("per_volume", per_volume), ("batched", batched)):
-        fn()
-        torch.cuda.synchronize()
-        best = 1e30
-        for _ in range(reps):
-            t0 = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            best = min(best, time.perf_counter() - t0)
-        res[name] = best * 1e3
+    pv = _best_ms(torch, per_volume, reps)
+    ref = [o.clone() for o in outs]
+    bt = _best_ms(torch, batched, reps)
+    same = all(torch.equal(a, b) for a, b in zip(ref, outs))
     U = sum(updates(c.shape[0]) for c in cubes)
-    return {"per_volume_ms": res["per_volume"], "batched_ms": res["batched"],
-            "speedup": res["per_volume"] / res["batched"], "updates": U,
-            "batched_updates_per_s": U / (res["batched"] / 1e3)}
+    return {"workload": "96 float32 N(0,1) cubes, seeds 1000+i: 48x32^3 + 32x64^3 + 12x128^3 + 4x256^3, "
+                        "12 dodecants",
+            "per_volume_ms": pv, "batched_ms": bt, "speedup": pv / bt, "bit_identical": same,
+            "updates": U, "batched_updates_per_s": U / (bt / 1e3)}
+
+
+def differentiable_speedup(api, torch, reps=5):
+    """Batch of 8 float32 N=128 cubes, 12 dodecants: forward + backward through
+    the autograd Function (batched launches) vs per-volume forward + adjoint."""
+    import workloads
+    from paper_2501_13664_amd import autograd
+    B, N = 8, 128
+    f = torch.from_numpy(workloads.normal_batch(B, N, seed=5)).cuda()
+    g = torch.from_numpy(workloads.normal_weights((B,) + api.drt3d_out_shape(N), seed=6)).cuda()
+    y = torch.empty_like(g)
+    x = torch.empty_like(f)
+
+    def per_volume():
+        for b in range(B):
+            api.drt3d_forward(f[b], out=y[b])
+            api.drt3d_adjoint(g[b], out=x[b])
+
+    fr = f.clone().requires_grad_(True)
+    state = {}
+
+    def differentiable():
+        fr.grad = None
+        out = autograd.drt3d(fr)
+        out.backward(g)
+        state["y"] = out
+
+    pv = _best_ms(torch, per_volume, reps)
+    ad = _best_ms(torch, differentiable, reps)
+    same = torch.equal(state["y"].detach(), y) and torch.equal(fr.grad, x)
+    U = 2 * B * updates(N)
+    return {"workload": "8 float32 N(0,1) cubes N=128 (seed 5), 12 dodecants, grad_out N(0,1) (seed 6)",
+            "per_volume_ms": pv, "autograd_ms": ad, "speedup": pv / ad, "bit_identical": same,
+            "updates": U, "autograd_updates_per_s": U / (ad / 1e3)}
+
+
+def copy_calibration(torch):
+    """Plain 1 GiB device copy, five times: the reference for the byte counters."""
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
+                      "launches": 5}), flush=True)
 
 
 def main():
@@ -106,6 +178,8 @@ def main():
     ap.add_argument("--N", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -113,6 +187,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     import workloads
     from paper_2501_13664_amd import api
 
@@ -178,6 +255,10 @@ def main():
     }
     if not args.no_batched:
         line["batched_vs_per_volume"] = batched_speedup(api, torch)
+        torch.cuda.empty_cache()
+    if not args.no_diff:
+        line["differentiable_vs_per_volume"] = differentiable_speedup(api, torch)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(vol_np)
     print(json.dumps(line), flush=True)

@@ -122,11 +122,16 @@ int drt3d_adjoint_batched(int count, const void* const* projs, void* const* vols
 
 /* ---- tuning ----------------------------------------------------------------- */
 /* Pick the stage grouping (stages fused per pass), tile width and LDS budget
- * for size class N and dtype by timing every candidate on the GPU with the given
- * buffers (vol: N^3, out: drt3d_out_elems(N, DRT3D_ALL), workspace of
- * drt3d_workspace_bytes(N, DRT3D_ALL, dtype)); `out` is clobbered. The choice is
- * kept for the process and, if the environment variable DRT3D_TUNE_CACHE names
- * a file, appended there. Every candidate computes bit-identical results. */
+ * (hence work groups per dodecant) and the wavefronts per work group for size
+ * class N and dtype by timing candidates on the GPU with the given buffers
+ * (vol: N^3, out: drt3d_out_elems(N, DRT3D_ALL), workspace of
+ * drt3d_workspace_bytes(N, DRT3D_ALL, dtype)); `out` is clobbered. The time
+ * minimised is the forward's for DRT3D_I32 and forward plus adjoint for
+ * DRT3D_F32; for the latter the call allocates (and frees) the adjoint's
+ * volume and workspace itself. The choice is kept for the process and, if the
+ * environment variable DRT3D_TUNE_CACHE names a file, appended there. int32
+ * results are bit-identical under every candidate; float32 results differ only
+ * by the order in which the stage sums are rounded. */
 int drt3d_autotune(int N, int dtype, const void* vol, void* out,
                    void* workspace, size_t workspace_bytes, void* stream);
 /* Current tuning choice of size class N as text (for logs and tests). */

@@ -589,7 +589,11 @@ constexpr int NW = 8;
 template <int KX>
 __device__ __forceinline__ int py_of(int wave, int i) { return (wave >> KX) + i * (NW >> KX); }
 
-template <typename T, int KX, int KY, int NCH>
+// FINAL: the forward's last pass, whose output columns are the caller's
+// projections. A column (s1, s2) is zero past dd = N-1+s1+s2 (the support of
+// eq. (9)), so a tile past the support of every column of the group is written
+// as zeros straight from registers, with no loads and no LDS stages.
+template <typename T, int KX, int KY, int NCH, bool FINAL>
 __global__ void __launch_bounds__(512)
 drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 {
@@ -617,6 +621,12 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
         const int vhy = (gy >> my0) << (my0 + KY);
         const int span = adjoint ? d->E_out + sx0 * ((1 << KX) - 1) + sy0 * ((1 << KY) - 1) : d->E_out;
         const int ntiles = min(d->ntiles, (span + T_ - 1) / T_);
+        // tiles [0, nlive) hold the group's support, the rest are zero (FINAL)
+        int nlive = ntiles;
+        if (FINAL) {
+            const int supp = N - 1 + (sx0 << KX) + (1 << KX) - 1 + (sy0 << KY) + (1 << KY) - 1;
+            nlive = min(ntiles, supp / T_ + 1);
+        }
         const FrameMap fm = d->fm[slot];
 
         // block column (px, py): c1 = sx0 + (px << mx0) + vhx, c2 = sy0 + (py << my0) + vhy
@@ -689,15 +699,18 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
         issue_loads(0);
         for (int tile = 0; tile < ntiles; ++tile) {
             const int d0 = tile * T_;
+            const bool live = !FINAL || tile < nlive;
+            if (live) {
 #pragma unroll
-            for (int i = 0; i < SPW; ++i) {
-                T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + lane;
+                for (int i = 0; i < SPW; ++i) {
+                    T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + lane;
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) sl[64 * c] = from_bits<T>(v[i][c]);
+                    for (int c = 0; c < NCH; ++c) sl[64 * c] = from_bits<T>(v[i][c]);
+                }
+                __syncthreads();
+                if (tile + 1 < nlive) issue_loads(d0 + T_);
+                run_stages<T, NCH>(lds, Lp, pad, NCH, KX, KY, adjoint, wave, NW, lane);
             }
-            __syncthreads();
-            if (tile + 1 < ntiles) issue_loads(d0 + T_);
-            run_stages<T, NCH>(lds, Lp, pad, NCH, KX, KY, adjoint, wave, NW, lane);
 
             // line-aligned store with carry (see store_tile_aligned)
             const bool last_tile = tile + 1 == ntiles;
@@ -718,7 +731,7 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
                     const int k = 64 * c + lane;
                     const int dd = fbeg + k;
                     if (k < cnt && (unsigned)dd < (unsigned)dE) {
-                        T val = dd < dd0 ? from_bits<T>(carry[i]) : sl[dd];
+                        T val = dd < dd0 ? from_bits<T>(carry[i]) : live ? sl[dd] : zero_of<T>();
                         const int off = 4 * (colo + dsd * dd);
                         if (accum) val += from_bits<T>(bload(rs_dst, off));
                         bstore(rs_dst, off, to_bits(val));
@@ -726,10 +739,10 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
                 }
                 if (!last_tile) {
                     const int tail = dd0 + T_ - fend;
-                    carry[i] = lane < tail ? to_bits(sl[fend + lane]) : 0u;
+                    carry[i] = lane < tail && live ? to_bits(sl[fend + lane]) : 0u;
                 }
             }
-            __syncthreads();
+            if (live) __syncthreads();
         }
     }
 }
@@ -740,14 +753,26 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 // out[b][c][r] (+)= in[b][r][c]; 64 x 64 tiles through LDS, 256 threads.
 template <typename T>
 __global__ void __launch_bounds__(256)
-transpose_kernel(const T* __restrict__ in, T* __restrict__ out, int R, int C, int add)
+transpose_kernel(const TransDesc* __restrict__ descs, int ndesc)
 {
     __shared__ T tile[64][65];
-    const long long b = blockIdx.z;
+    const long long wg = blockIdx.x;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].wg_begin <= wg) lo = mid; else hi = mid - 1;
+    }
+    const TransDesc& d = descs[lo];
+    long long local = wg - d.wg_begin;
+    const int tc = (int)(local % d.tiles_c);
+    local /= d.tiles_c;
+    const int tr = (int)(local % d.tiles_r);
+    const long long b = local / d.tiles_r;
+    const int R = d.R, C = d.C;
     const long long plane = (long long)R * C;
-    const T* src = in + b * plane;
-    T* dst = out + b * plane;
-    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+    const T* src = reinterpret_cast<const T*>(d.in) + b * plane;
+    T* dst = reinterpret_cast<T*>(d.out) + b * plane;
+    const int c0 = tc * 64, r0 = tr * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -761,7 +786,7 @@ transpose_kernel(const T* __restrict__ in, T* __restrict__ out, int R, int C, in
         if (r < R && c < C) {
             const long long o = (long long)c * R + r;
             const T v = tile[tx][ty + 4 * i];
-            dst[o] = add ? dst[o] + v : v;
+            dst[o] = d.add ? dst[o] + v : v;
         }
     }
 }
@@ -855,10 +880,12 @@ djt_stage_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_w
 
 // ---------------------------------------------------------------------------
 template <typename T>
-static const void* fast_kernel(int kx, int ky, int nch)
+static const void* fast_kernel(int kx, int ky, int nch, bool final_pass)
 {
-#define DRT3D_FAST(KX, KY, NC) \
-    if (kx == KX && ky == KY && nch == NC) return reinterpret_cast<const void*>(&fast::drt_pass_fast<T, KX, KY, NC>);
+#define DRT3D_FAST(KX, KY, NC)                                                                             \
+    if (kx == KX && ky == KY && nch == NC)                                                                 \
+        return final_pass ? reinterpret_cast<const void*>(&fast::drt_pass_fast<T, KX, KY, NC, true>)       \
+                          : reinterpret_cast<const void*>(&fast::drt_pass_fast<T, KX, KY, NC, false>);
 #define DRT3D_FAST_NCH(KX, KY) \
     DRT3D_FAST(KX, KY, 1) DRT3D_FAST(KX, KY, 2) DRT3D_FAST(KX, KY, 3) DRT3D_FAST(KX, KY, 4) \
     DRT3D_FAST(KX, KY, 5) DRT3D_FAST(KX, KY, 6)
@@ -876,11 +903,12 @@ static hipError_t set_fast_lds_limit(size_t bytes)
 {
     const int shapes[4][2] = {{3, 3}, {2, 2}, {3, 2}, {2, 3}};
     for (auto& sh : shapes)
-        for (int nc = 1; nc <= 6; ++nc) {
-            hipError_t e = hipFuncSetAttribute(fast_kernel<T>(sh[0], sh[1], nc),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-            if (e != hipSuccess) return e;
-        }
+        for (int nc = 1; nc <= 6; ++nc)
+            for (int fin = 0; fin < 2; ++fin) {
+                hipError_t e = hipFuncSetAttribute(fast_kernel<T>(sh[0], sh[1], nc, fin != 0),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+                if (e != hipSuccess) return e;
+            }
     return hipSuccess;
 }
 
@@ -897,12 +925,13 @@ hipError_t set_drt_lds_limit(int is_float, size_t bytes)
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-int drt_fast_available(int kx, int ky, int nch) { return fast_kernel<uint32_t>(kx, ky, nch) != nullptr; }
+int drt_fast_available(int kx, int ky, int nch) { return fast_kernel<uint32_t>(kx, ky, nch, false) != nullptr; }
 
-hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, const DrtDesc* d_descs, int ndesc,
-                           long long total_wg, int grid, size_t lds_bytes, hipStream_t s)
+hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int final_pass, const DrtDesc* d_descs,
+                           int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s)
 {
-    const void* k = is_float ? fast_kernel<float>(kx, ky, nch) : fast_kernel<uint32_t>(kx, ky, nch);
+    const void* k = is_float ? fast_kernel<float>(kx, ky, nch, final_pass != 0)
+                             : fast_kernel<uint32_t>(kx, ky, nch, final_pass != 0);
     if (!k) return hipErrorInvalidValue;
     void* args[] = {&d_descs, &ndesc, &total_wg};
     return hipLaunchKernel(k, dim3(grid), dim3(512), args, lds_bytes, s);
@@ -930,16 +959,15 @@ hipError_t launch_djt_stage(int is_float, const DjtDesc* d_descs, int ndesc, lon
     return hipGetLastError();
 }
 
-hipError_t launch_transpose(int is_float, const void* in, void* out, int R, int C, int batches, int add,
+hipError_t launch_transpose(int is_float, const TransDesc* d_descs, int ndesc, long long total_wg,
                             hipStream_t s)
 {
-    dim3 grid((C + 63) / 64, (R + 63) / 64, batches);
+    if (total_wg <= 0) return hipSuccess;
+    if (total_wg > 0x7fffffffLL) return hipErrorInvalidValue;
     if (is_float)
-        hipLaunchKernelGGL(transpose_kernel<float>, grid, dim3(256), 0, s, reinterpret_cast<const float*>(in),
-                           reinterpret_cast<float*>(out), R, C, add);
+        hipLaunchKernelGGL(transpose_kernel<float>, dim3((unsigned)total_wg), dim3(256), 0, s, d_descs, ndesc);
     else
-        hipLaunchKernelGGL(transpose_kernel<uint32_t>, grid, dim3(256), 0, s,
-                           reinterpret_cast<const uint32_t*>(in), reinterpret_cast<uint32_t*>(out), R, C, add);
+        hipLaunchKernelGGL(transpose_kernel<uint32_t>, dim3((unsigned)total_wg), dim3(256), 0, s, d_descs, ndesc);
     return hipGetLastError();
 }
 

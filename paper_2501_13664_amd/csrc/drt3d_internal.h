@@ -58,18 +58,29 @@ struct DjtDesc {
     FrameMap fm[kMaxSlots];
 };
 
+// One transpose out[b][c][r] (+)= in[b][r][c], b < batches, r < R, c < C, in
+// 64 x 64 tiles; work items are (b, tile row, tile column) flattened, from
+// `wg_begin` inside the launch.
+struct TransDesc {
+    long long wg_begin;
+    const void* in;
+    void* out;
+    int R, C, batches, add;
+    int tiles_r, tiles_c;
+};
+
 // Launchers (device code translation unit).
 hipError_t launch_drt_pass(int is_float, const DrtDesc* d_descs, int ndesc, long long total_wg,
                            int block, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_djt_stage(int is_float, const DjtDesc* d_descs, int ndesc, long long total_wg,
                             int block, int grid, hipStream_t s);
-// out[b][c][r] (+)= in[b][r][c], for b < batches, r < R, c < C.
-hipError_t launch_transpose(int is_float, const void* in, void* out, int R, int C, int batches,
-                            int add, hipStream_t s);
+hipError_t launch_transpose(int is_float, const TransDesc* d_descs, int ndesc, long long total_wg,
+                            hipStream_t s);
 hipError_t set_drt_lds_limit(int is_float, size_t bytes);
 // Shape-specialised DRT pass kernels (eight wavefronts per work group).
+// final_pass: every descriptor is the forward's last pass (caller's output).
 int drt_fast_available(int kx, int ky, int nch);
-hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, const DrtDesc* d_descs, int ndesc,
-                           long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int final_pass, const DrtDesc* d_descs,
+                           int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
 
 }  // namespace drt3d

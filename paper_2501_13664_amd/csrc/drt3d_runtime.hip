@@ -183,17 +183,44 @@ struct Tuning {
 static const int kMaxPassSlots = 256;  // 2^(kx+ky) columns per group at most
 
 // Default: as few passes as fit 64-column groups, stages spread evenly.
-static Tuning default_tuning(int n)
+static bool tuning_from_string(const char* s, int n, Tuning& t);
+
+// Rule for size classes without a measured entry: passes of at most 3 x- and
+// 3 y-stages, as even as possible, the shorter ones first (the early stage
+// buffers are the narrow ones).
+static Tuning rule_tuning(int n)
 {
     Tuning t;
-    int P = (n + 2) / 3;  // passes of at most 3 x- and 3 y-stages
+    int P = (n + 2) / 3;
     if (P < 1) P = 1;
     t.np = P;
     for (int i = 0; i < P; ++i) {
-        t.kx[i] = n / P + (i < n % P ? 1 : 0);
+        t.kx[i] = n / P + (i >= P - n % P ? 1 : 0);
         t.ky[i] = t.kx[i];
     }
     return t;
+}
+
+// Choices of drt3d_autotune on an MI355X (gfx950), per size class and dtype.
+struct MeasuredTuning {
+    int n, is_float;
+    const char* text;
+};
+static const MeasuredTuning kMeasured[] = {
+    {5, 0, "p=3.3,2.2;lds=13312;waves=8"},     {5, 1, "p=2.2,3.3;lds=16384;waves=8"},
+    {6, 0, "p=3.3,3.3;lds=20480;waves=8"},     {6, 1, "p=3.3,3.3;lds=24576;waves=8"},
+    {7, 0, "p=2.2,2.3,3.2;lds=12288;waves=8"}, {7, 1, "p=2.2,2.3,3.2;lds=14336;waves=8"},
+    {8, 0, "p=3.3,2.3,3.2;lds=14336;waves=8"}, {8, 1, "p=2.3,3.3,3.2;lds=24576;waves=8"},
+    {9, 0, "p=3.3,3.3,3.3;lds=14336;waves=8"}, {9, 1, "p=3.3,3.3,3.3;lds=14336;waves=8"},
+};
+
+static Tuning default_tuning(int n, int is_float)
+{
+    for (const MeasuredTuning& m : kMeasured) {
+        Tuning t;
+        if (m.n == n && m.is_float == is_float && tuning_from_string(m.text, n, t)) return t;
+    }
+    return rule_tuning(n);
 }
 
 static std::string tuning_to_string(const Tuning& t)
@@ -251,7 +278,7 @@ static Tuning get_tuning(int N, int is_float)
     auto it = g_tuning.find({N, is_float});
     if (it != g_tuning.end()) return it->second;
     const int n = ilog2_exact(N);
-    Tuning t = default_tuning(n);
+    Tuning t = default_tuning(n, is_float);
     if (const char* path = getenv("DRT3D_TUNE_CACHE")) {
         if (FILE* fp = fopen(path, "r")) {
             char line[256];
@@ -366,14 +393,13 @@ struct Launch {
     int kind;
     std::string name;
     int fast_kx = -1, fast_ky = -1, fast_nch = -1;  // shape-specialised DRT kernel, if any
+    int fast_final = 0;                             // ... its forward-last-pass form
     int first = 0, ndesc = 0;
     long long total_wg = 0;
+    int persistent = 0;  // grid capped at a few work groups per CU, looping over the items
     int block = 64;
     size_t lds = 0;
     double bytes = 0;
-    const void* t_in = nullptr;
-    void* t_out = nullptr;
-    int t_R = 0, t_C = 0, t_batches = 0, t_add = 0;
 };
 
 struct Program {
@@ -381,40 +407,69 @@ struct Program {
     int persistent = 0;
     std::vector<DrtDesc> drt;
     std::vector<DjtDesc> djt;
+    std::vector<TransDesc> tr;
     std::vector<Launch> launches;
     size_t drt_bytes() const { return align256(drt.size() * sizeof(DrtDesc)); }
-    size_t desc_bytes() const { return drt_bytes() + align256(djt.size() * sizeof(DjtDesc)); }
+    size_t djt_bytes() const { return align256(djt.size() * sizeof(DjtDesc)); }
+    size_t desc_bytes() const { return drt_bytes() + djt_bytes() + align256(tr.size() * sizeof(TransDesc)); }
 };
 
 // Append the steps as launches, in order (single calls) or merged by key
-// (batched calls: all steps with the same key form one launch).
-static void build_program(Program& prog, const std::vector<std::vector<Step>>& per_volume, bool merge)
+// (batched calls: all steps with the same key form one launch). Volumes
+// marked `solo` are never merged: their steps follow the merged launches in
+// per-volume order, so each volume's freshly written buffers are read while
+// they may still sit in the memory-side cache.
+static void build_program(Program& prog, const std::vector<std::vector<Step>>& per_volume, bool merge,
+                          const std::vector<char>* solo = nullptr)
 {
     std::vector<const Step*> order;
+    std::vector<char> mergeable;
     if (!merge) {
         for (auto& v : per_volume)
-            for (auto& s : v) order.push_back(&s);
+            for (auto& s : v) { order.push_back(&s); mergeable.push_back(0); }
     } else {
         std::map<int, std::vector<const Step*>> bykey;
-        for (auto& v : per_volume)
-            for (auto& s : v) bykey[s.key].push_back(&s);
+        for (size_t i = 0; i < per_volume.size(); ++i)
+            if (!solo || !(*solo)[i])
+                for (auto& s : per_volume[i]) bykey[s.key].push_back(&s);
         for (auto& kv : bykey)
-            for (auto* s : kv.second) order.push_back(s);
+            for (auto* s : kv.second) { order.push_back(s); mergeable.push_back(1); }
+        if (solo)
+            for (size_t i = 0; i < per_volume.size(); ++i)
+                if ((*solo)[i])
+                    for (auto& s : per_volume[i]) { order.push_back(&s); mergeable.push_back(0); }
     }
     size_t i = 0;
     while (i < order.size()) {
         const Step* s0 = order[i];
         size_t j = i + 1;
-        if (merge && s0->kind != S_TRANSPOSE)
-            while (j < order.size() && order[j]->key == s0->key && order[j]->kind == s0->kind &&
+        if (mergeable[i])
+            while (j < order.size() && mergeable[j] && order[j]->key == s0->key && order[j]->kind == s0->kind &&
                    order[j]->shape == s0->shape)
                 ++j;
         Launch L;
         L.kind = s0->kind;
         L.name = s0->name;
+        L.persistent = prog.persistent && mergeable[i];
         if (s0->kind == S_TRANSPOSE) {
-            L.t_in = s0->t_in; L.t_out = s0->t_out; L.t_R = s0->t_R; L.t_C = s0->t_C;
-            L.t_batches = s0->t_batches; L.t_add = s0->t_add; L.bytes = s0->bytes;
+            // steps of one key write different volumes: one launch is race-free
+            L.first = (int)prog.tr.size();
+            long long wg = 0;
+            for (size_t q = i; q < j; ++q) {
+                const Step* t = order[q];
+                TransDesc d{};
+                d.wg_begin = wg;
+                d.in = t->t_in; d.out = t->t_out; d.R = t->t_R; d.C = t->t_C;
+                d.batches = t->t_batches; d.add = t->t_add;
+                d.tiles_r = (t->t_R + 63) / 64;
+                d.tiles_c = (t->t_C + 63) / 64;
+                wg += (long long)d.tiles_r * d.tiles_c * d.batches;
+                prog.tr.push_back(d);
+                L.bytes += t->bytes;
+            }
+            L.ndesc = (int)prog.tr.size() - L.first;
+            L.total_wg = wg;
+            L.block = 256;
             prog.launches.push_back(L);
             i = j;
             continue;
@@ -451,17 +506,19 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
         if (s0->kind == S_DRT && L.block == 512) {
             // one shape across the launch's descriptors -> specialised kernel
             const DrtDesc& f = prog.drt[L.first];
-            bool same = true;
+            bool same = true, final_pass = true;
             for (int q = L.first; q < L.first + L.ndesc; ++q) {
                 const DrtDesc& e = prog.drt[q];
                 // the specialised kernel addresses each region with 32-bit
                 // byte offsets: N <= 512 keeps every region below 2^31 bytes
                 same = same && e.Kx == f.Kx && e.Ky == f.Ky && e.L == f.L && e.N <= 512;
+                final_pass = final_pass && !e.adjoint && e.dst_mode == 0 && e.nt_store;
             }
             if (same && (f.L & 63) == 0 && drt_fast_available(f.Kx, f.Ky, f.L >> 6)) {
                 L.fast_kx = f.Kx;
                 L.fast_ky = f.Ky;
                 L.fast_nch = f.L >> 6;
+                L.fast_final = final_pass;
             }
         }
         prog.launches.push_back(L);
@@ -504,6 +561,8 @@ static int upload_descs(const Program& p, void* d_area, hipStream_t s)
     memset(h, 0, bytes);
     if (!p.drt.empty()) memcpy(h, p.drt.data(), p.drt.size() * sizeof(DrtDesc));
     if (!p.djt.empty()) memcpy(h + p.drt_bytes(), p.djt.data(), p.djt.size() * sizeof(DjtDesc));
+    if (!p.tr.empty())
+        memcpy(h + p.drt_bytes() + p.djt_bytes(), p.tr.data(), p.tr.size() * sizeof(TransDesc));
     HIP_TRY(hipMemcpyAsync(d_area, h, bytes, hipMemcpyHostToDevice, s));
     HIP_TRY(hipEventRecord(st.ev[i], s));
     return DRT3D_OK;
@@ -519,6 +578,7 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
 {
     const DrtDesc* d_drt = reinterpret_cast<const DrtDesc*>(d_area);
     const DjtDesc* d_djt = reinterpret_cast<const DjtDesc*>((char*)d_area + p.drt_bytes());
+    const TransDesc* d_tr = reinterpret_cast<const TransDesc*>((char*)d_area + p.drt_bytes() + p.djt_bytes());
     const bool prof = g_prof_on.load() != 0;
     for (const Launch& L : p.launches) {
         hipEvent_t ea = nullptr, eb = nullptr;
@@ -533,16 +593,16 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
                 return fail(DRT3D_EINVAL, "%s needs %zu bytes of LDS, the device allows %d", L.name.c_str(), L.lds,
                             di.max_lds);
             if (L.fast_kx >= 0)
-                e = launch_drt_fast(p.is_float, L.fast_kx, L.fast_ky, L.fast_nch, d_drt + L.first, L.ndesc,
-                                    L.total_wg, grid_for(L.total_wg, di, p.persistent), L.lds, s);
+                e = launch_drt_fast(p.is_float, L.fast_kx, L.fast_ky, L.fast_nch, L.fast_final, d_drt + L.first, L.ndesc,
+                                    L.total_wg, grid_for(L.total_wg, di, L.persistent), L.lds, s);
             else
                 e = launch_drt_pass(p.is_float, d_drt + L.first, L.ndesc, L.total_wg, L.block,
-                                    grid_for(L.total_wg, di, p.persistent), L.lds, s);
+                                    grid_for(L.total_wg, di, L.persistent), L.lds, s);
         } else if (L.kind == S_DJT) {
             e = launch_djt_stage(p.is_float, d_djt + L.first, L.ndesc, L.total_wg, L.block,
-                                 grid_for(L.total_wg, di, p.persistent), s);
+                                 grid_for(L.total_wg, di, L.persistent), s);
         } else {
-            e = launch_transpose(p.is_float, L.t_in, L.t_out, L.t_R, L.t_C, L.t_batches, L.t_add, s);
+            e = launch_transpose(p.is_float, d_tr + L.first, L.ndesc, L.total_wg, s);
         }
         if (e != hipSuccess)
             return fail(DRT3D_EHIP, "launch of %s failed: %s", L.name.c_str(), hipGetErrorString(e));
@@ -613,6 +673,15 @@ static int pass_pad(const PassGeom& g)
 
 static long long lds_elems_of(int nslot, int L, int pad) { return (long long)nslot * (L + pad) + pad; }
 
+// Longest LDS column the shape-specialised kernels of a (Kx, Ky) pass take
+// (0: the shape has none). Longer columns would fall back to the generic kernel.
+static int fast_max_L(const PassGeom& g)
+{
+    for (int nch = 16; nch >= 1; --nch)
+        if (drt_fast_available(g.Kx, g.Ky, nch)) return 64 * nch;
+    return 0;
+}
+
 static bool choose_tiles(const PassGeom& g, int adjoint, int lds_elems, int& T, int& H, int& L, int& ntiles)
 {
     const int ns = 1 << (g.Kx + g.Ky);
@@ -623,7 +692,9 @@ static bool choose_tiles(const PassGeom& g, int adjoint, int lds_elems, int& T, 
     const int E = adjoint ? g.E_in : g.E_out;  // extent written
     const int skew = adjoint ? ((1 << g.mx0) - 1) * ((1 << g.Kx) - 1) + ((1 << g.my0) - 1) * ((1 << g.Ky) - 1) : 0;
     const int span = E + skew;
-    const int Lmax = (int)(((lds_elems - pad) / ns - pad) & ~63LL);
+    int Lmax = (int)(((lds_elems - pad) / ns - pad) & ~63LL);
+    const int Lfast = fast_max_L(g);
+    if (Lfast > 0 && Lmax > Lfast && Lfast - H >= 32) Lmax = Lfast;
     if (Lmax - H < 32) return false;  // tiles of at least one 128-byte line
     ntiles = (span + (Lmax - H) - 1) / (Lmax - H);
     const int Tmin = (span + ntiles - 1) / ntiles;
@@ -911,9 +982,8 @@ static std::string program_signature(const Program& p, void* d_area)
     snprintf(buf, sizeof buf, "%p|%d|", d_area, p.is_float);
     sig += buf;
     for (const Launch& L : p.launches) {
-        snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%zu:%p:%p:%d:%d:%d:%d:%d.%d.%d;", L.kind, L.first, L.ndesc,
-                 L.total_wg, L.block, L.lds, L.t_in, L.t_out, L.t_R, L.t_C, L.t_batches, L.t_add, L.fast_kx,
-                 L.fast_ky, L.fast_nch);
+        snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%d:%zu:%d.%d.%d;", L.kind, L.first, L.ndesc, L.total_wg,
+                 L.persistent, L.block, L.lds, L.fast_kx, L.fast_ky, L.fast_nch + 8 * L.fast_final);
         sig += buf;
     }
     return sig;
@@ -999,7 +1069,8 @@ static size_t desc_area_bytes(int kind, int N, uint32_t mask, int chunked)
     }
     const int c = chunked ? chunk_size(2 * drt_stage_elems_per_dod(N) * 4, nd) : nd;
     cnt = (size_t)((nd + c - 1) / c) * (2 * n + 4);  // passes (<= 2n) + adjoint rounds
-    return align256(cnt * sizeof(DrtDesc)) + 256;
+    // + the two volume transposes
+    return align256(cnt * sizeof(DrtDesc)) + align256(2 * sizeof(TransDesc)) + 256;
 }
 
 }  // namespace drt3d
@@ -1121,6 +1192,9 @@ int djt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype, v
     return execute(prog, workspace, (hipStream_t)stream, di, 0);
 }
 
+// Batched calls merge the launches of volumes below this size.
+static const int kSoloN = 128;
+
 static int batched(int kind, int adjoint, int count, const void* const* ins, void* const* outs, const int* Ns,
                    uint32_t mask, int dtype, void* ws, size_t ws_bytes, void* stream)
 {
@@ -1139,7 +1213,11 @@ static int batched(int kind, int adjoint, int count, const void* const* ins, voi
     for (int i = 0; i < count; ++i) dsz += desc_area_bytes(kind, Ns[i], mask, 0);
     char* w = (char*)ws + align256(dsz);
     std::vector<std::vector<Step>> vols(count);
+    std::vector<char> solo(count, 0);
     for (int i = 0; i < count; ++i) {
+        // a volume this large fills the GPU in every launch on its own:
+        // merging it with others only stretches each launch's working set
+        solo[i] = Ns[i] >= kSoloN;
         DrtIO io{ins[i], outs[i], w};
         if (kind == S_DJT) {
             TRY(djt_steps(vols[i], Ns[i], mask, 0, io));
@@ -1152,7 +1230,7 @@ static int batched(int kind, int adjoint, int count, const void* const* ins, voi
     Program prog;
     prog.is_float = is_float;
     prog.persistent = 1;
-    build_program(prog, vols, true);
+    build_program(prog, vols, true, &solo);
     if (prog.desc_bytes() > align256(dsz)) return fail(DRT3D_EINVAL, "internal: descriptor area too small");
     const char* g = getenv("DRT3D_GRAPHS");
     const int use_graph = g ? atoi(g) != 0 : 1;
@@ -1203,22 +1281,29 @@ int drt3d_set_tuning(int N, int dtype, const char* text)
     return DRT3D_OK;
 }
 
-// Distinct orderings of the most even split of n stages into P passes.
-static void even_splits(int n, int P, std::vector<std::vector<int>>& out)
+// Splits of n stages into P passes of 1..3 stages each, in every order.
+static void stage_splits(int n, int P, std::vector<std::vector<int>>& out)
 {
-    std::vector<int> k(P);
-    for (int i = 0; i < P; ++i) k[i] = n / P + (i < n % P ? 1 : 0);
-    std::sort(k.begin(), k.end());
-    do out.push_back(k); while (std::next_permutation(k.begin(), k.end()));
+    std::vector<int> k(P, 1);
+    for (;;) {
+        int sum = 0;
+        for (int v : k) sum += v;
+        if (sum == n) out.push_back(k);
+        int i = 0;
+        while (i < P && k[i] == 3) k[i++] = 1;
+        if (i == P) break;
+        ++k[i];
+    }
 }
 
-// Candidate pass lists: 1..4 passes, each axis split as evenly as possible in
-// every distinct order, groups of at most kMaxPassSlots columns.
+// Candidate pass lists: ceil(n/3)..ceil(n/3)+1 passes (at most 4); per pass the
+// x- and y-stage counts differ by at most one (square-ish column groups).
 static void pass_list_candidates(int n, const Tuning& base, std::vector<Tuning>& out)
 {
-    for (int P = 1; P <= std::min(4, n); ++P) {
+    const int P0 = std::max(1, (n + 2) / 3);
+    for (int P = P0; P <= std::min(std::min(4, n), P0 + 1); ++P) {
         std::vector<std::vector<int>> xs;
-        even_splits(n, P, xs);
+        stage_splits(n, P, xs);
         for (auto& a : xs)
             for (auto& b : xs) {
                 Tuning c = base;
@@ -1227,13 +1312,18 @@ static void pass_list_candidates(int n, const Tuning& base, std::vector<Tuning>&
                 for (int i = 0; i < P; ++i) {
                     c.kx[i] = a[i];
                     c.ky[i] = b[i];
-                    if ((1 << (a[i] + b[i])) > kMaxPassSlots) ok = false;
+                    if (std::abs(a[i] - b[i]) > 1 || (1 << (a[i] + b[i])) > kMaxPassSlots) ok = false;
                 }
                 if (ok) out.push_back(c);
             }
     }
 }
 
+// Timed search over the tuning space of one size class. Objective: forward
+// time for int32, forward + adjoint time for float32 (the differentiable
+// transform runs both). Phase 1 times every pass list at two LDS budgets,
+// phase 2 every LDS budget for the three best lists, phase 3 the wave count.
+// The adjoint's buffers are allocated here (a tuning call, not a transform).
 int drt3d_autotune(int N, int dtype, const void* vol, void* out, void* workspace, size_t workspace_bytes,
                    void* stream)
 {
@@ -1246,6 +1336,16 @@ int drt3d_autotune(int N, int dtype, const void* vol, void* out, void* workspace
     const int n = ilog2_exact(N);
     const int is_float = dtype == DRT3D_F32;
     hipStream_t s = (hipStream_t)stream;
+    void* back = nullptr;
+    void* aws = nullptr;
+    const size_t aws_bytes = drt3d_adjoint_workspace_bytes(N, DRT3D_ALL, dtype);
+    if (is_float) {
+        HIP_TRY(hipMalloc(&back, (size_t)N * N * N * 4));
+        if (hipMalloc(&aws, aws_bytes) != hipSuccess) {
+            (void)hipFree(back);
+            return fail(DRT3D_ENOMEM, "autotune: no memory for the adjoint workspace");
+        }
+    }
     hipEvent_t ea, eb;
     HIP_TRY(hipEventCreate(&ea));
     HIP_TRY(hipEventCreate(&eb));
@@ -1255,6 +1355,7 @@ int drt3d_autotune(int N, int dtype, const void* vol, void* out, void* workspace
         for (int r = 0; r < 4; ++r) {
             HIP_TRY(hipEventRecord(ea, s));
             TRY(drt3d_forward(vol, out, N, DRT3D_ALL, dtype, workspace, workspace_bytes, stream));
+            if (is_float) TRY(drt3d_adjoint(out, back, N, DRT3D_ALL, dtype, aws, aws_bytes, stream));
             HIP_TRY(hipEventRecord(eb, s));
             HIP_TRY(hipEventSynchronize(eb));
             float ms = 0;
@@ -1272,31 +1373,60 @@ int drt3d_autotune(int N, int dtype, const void* vol, void* out, void* workspace
             }
         return true;
     };
+    int rc = DRT3D_OK;
     Tuning best = get_tuning(N, is_float);
-    if (!fits(best)) best = default_tuning(n);
-    float best_ms;
-    TRY(time_of(best, best_ms));
-    const int lds_opts[] = {8192, 12288, 16384, 18432, 24576, 32768, 38912};
-    const int wave_opts[] = {4, 8};
-    for (int round = 0; round < 2; ++round) {
-        for (int dim = 0; dim < 3; ++dim) {
-            std::vector<Tuning> cands;
-            if (dim == 0) pass_list_candidates(n, best, cands);
-            else if (dim == 1)
-                for (int l : lds_opts) { Tuning c = best; c.lds_elems = l; cands.push_back(c); }
-            else
-                for (int w : wave_opts) { Tuning c = best; c.waves = w; cands.push_back(c); }
-            for (const Tuning& c : cands) {
-                if (!fits(c) || tuning_to_string(c) == tuning_to_string(best)) continue;
-                float ms;
-                TRY(time_of(c, ms));
-                if (ms < best_ms * 0.98f) { best_ms = ms; best = c; }
+    if (!fits(best)) best = default_tuning(n, is_float);
+    float best_ms = 1e30f;
+    std::vector<std::pair<float, Tuning>> scored;
+    auto consider = [&](const Tuning& c) -> int {
+        if (!fits(c)) return DRT3D_OK;
+        float ms;
+        TRY(time_of(c, ms));
+        scored.push_back({ms, c});
+        if (ms < best_ms) { best_ms = ms; best = c; }
+        return DRT3D_OK;
+    };
+    do {
+        if ((rc = consider(best)) != DRT3D_OK) break;
+        std::vector<Tuning> lists;
+        pass_list_candidates(n, best, lists);
+        for (Tuning c : lists) {
+            for (int l : {16384, 18432}) {
+                c.lds_elems = l;
+                c.waves = 8;
+                if ((rc = consider(c)) != DRT3D_OK) break;
             }
+            if (rc != DRT3D_OK) break;
         }
-    }
+        if (rc != DRT3D_OK) break;
+        std::sort(scored.begin(), scored.end(),
+                  [](const std::pair<float, Tuning>& x, const std::pair<float, Tuning>& y) { return x.first < y.first; });
+        std::vector<Tuning> top;
+        for (auto& sc : scored) {
+            bool dup = false;
+            for (auto& t : top) dup = dup || (t.np == sc.second.np && std::equal(t.kx, t.kx + t.np, sc.second.kx) &&
+                                              std::equal(t.ky, t.ky + t.np, sc.second.ky));
+            if (!dup) top.push_back(sc.second);
+            if (top.size() == 3) break;
+        }
+        for (Tuning c : top) {
+            for (int l : {8192, 12288, 13312, 14336, 20480, 24576, 32768}) {
+                c.lds_elems = l;
+                if ((rc = consider(c)) != DRT3D_OK) break;
+            }
+            if (rc != DRT3D_OK) break;
+        }
+        if (rc != DRT3D_OK) break;
+        Tuning c = best;
+        c.waves = 4;
+        rc = consider(c);
+    } while (0);
     put_tuning(N, is_float, best);
     (void)hipEventDestroy(ea);
     (void)hipEventDestroy(eb);
+    if (back) (void)hipFree(back);
+    if (aws) (void)hipFree(aws);
+    if (rc != DRT3D_OK) return rc;
     if (const char* path = getenv("DRT3D_TUNE_CACHE")) {
         if (FILE* fp = fopen(path, "a")) {
             fprintf(fp, "%d %d %s\n", N, is_float, tuning_to_string(best).c_str());
@@ -1369,9 +1499,7 @@ int drt3d_plan_text(int op, int N, uint32_t mask, int dtype, char* buf, size_t c
     char line[256];
     for (const Launch& L : prog.launches) {
         snprintf(line, sizeof line, "%s kind=%d wg=%lld block=%d lds=%zu bytes=%.0f\n", L.name.c_str(), L.kind,
-                 L.kind == S_TRANSPOSE ? (long long)((L.t_C + 63) / 64) * ((L.t_R + 63) / 64) * L.t_batches
-                                       : L.total_wg,
-                 L.kind == S_TRANSPOSE ? 256 : L.block, L.lds, L.bytes);
+                 L.total_wg, L.block, L.lds, L.bytes);
         txt += line;
     }
     if (buf && cap) {

@@ -432,3 +432,23 @@ def test_workload_generators_are_seeded():
     assert [x.shape[0] for x in cubes] == [4, 4, 8] and cubes[0].dtype == np.float32
     cc = workloads.corners_and_centre(8)
     assert cc.sum() == 9
+
+
+# ------------------------------------------------------------ sparse matrix
+def test_sparse_matrix_reproduces_definition_and_adjoint():
+    """The column-by-column matrix used by the gradient checks equals the
+    definition on a random cube, its transpose equals the adjoint definition,
+    and every voxel meets exactly one displacement per (dodecant, s1, s2)."""
+    import oracle as O
+    from tests.sparse_ref import drt_matrix
+    N = 8
+    R = drt_matrix(N)
+    assert R.nnz == 12 * N * N * N ** 3 and R.max() == 1
+    rng = np.random.default_rng(21)
+    f = rng.integers(-9, 9, size=(N, N, N)).astype(np.int32)
+    assert np.array_equal((R @ f.ravel().astype(np.float64)).astype(np.int64), O.def_drt(f).ravel())
+    p = rng.integers(-9, 9, size=(12, N, N, 3 * N - 2)).astype(np.int32)
+    assert np.array_equal((R.T @ p.ravel().astype(np.float64)).astype(np.int64), O.def_adj(p, N).ravel())
+    Rk = drt_matrix(N, 0b000100000010)
+    assert np.array_equal((Rk @ f.ravel().astype(np.float64)).astype(np.int64),
+                          O.def_drt(f, 0b000100000010).ravel())

@@ -13,7 +13,8 @@ import numpy as np
 
 __all__ = [
     "uniform_int_cube", "normal_cube", "point_cloud_with_planes",
-    "noise_with_segments", "mixed_batch", "corners_and_centre", "WORKLOADS",
+    "noise_with_segments", "mixed_batch", "corners_and_centre", "normal_batch",
+    "normal_weights", "random_voxels", "WORKLOADS",
 ]
 
 
@@ -97,6 +98,28 @@ def mixed_batch(counts=((32, 48), (64, 32), (128, 12), (256, 4)), seed0: int = 1
     return cubes
 
 
+def normal_batch(B: int = 8, N: int = 128, seed: int = 5) -> np.ndarray:
+    """float32 [B][N][N][N], values N(0,1), drawn in order from one stream."""
+    rng = _rng(seed)
+    return rng.standard_normal(size=(B, N, N, N), dtype=np.float32)
+
+
+def normal_weights(shape, seed: int = 6) -> np.ndarray:
+    """float32 N(0,1) weights of the given shape (e.g. shaped like a batch of
+    transforms), drawn in C order from one stream."""
+    return _rng(seed).standard_normal(size=tuple(shape), dtype=np.float32)
+
+
+def random_voxels(count: int, B: int, N: int, seed: int = 7) -> np.ndarray:
+    """[count][4] int64 (b, x, y, z) positions, distinct, uniform over a batch."""
+    rng = _rng(seed)
+    flat = rng.choice(B * N ** 3, size=count, replace=False)
+    b, r = np.divmod(flat, N ** 3)
+    x, r = np.divmod(r, N * N)
+    y, z = np.divmod(r, N)
+    return np.stack([b, x, y, z], axis=1).astype(np.int64)
+
+
 def corners_and_centre(N: int = 64, value: int = 1) -> np.ndarray:
     """int32 cube with the 8 corner voxels and the centre voxel set (Sec. 5.1)."""
     vol = np.zeros((N, N, N), dtype=np.int32)
@@ -116,4 +139,8 @@ WORKLOADS = {
                                        make=lambda: point_cloud_with_planes(512, seed=2)),
     "djt_n128_segments": dict(kind="djt", N=128, dtype="int32",
                               make=lambda: noise_with_segments(128, seed=3)),
+    "drt_batch_mixed_f32": dict(kind="drt_batched", N=(32, 64, 128, 256), dtype="float32",
+                                make=lambda: mixed_batch()),
+    "drt_diff_b8_n128_f32": dict(kind="drt_autograd", N=128, dtype="float32",
+                                 make=lambda: normal_batch(8, 128, seed=5)),
 }
