@@ -15,11 +15,13 @@ the committed rocprofv3 counter summary when it was taken on the current
 sources. `cpu_baseline` times the oracle's naive Algorithm 1 on one dodecant of
 the same cube (scaled to the job).
 
-Two further measurements ride along (skipped with --no-batched / --no-diff):
-the batched forward of 96 float32 cubes of mixed N against per-volume calls,
-and the differentiable transform (forward + backward through autograd) of a
-batch of 8 float32 N=128 cubes against per-volume forward + adjoint calls;
-both check that the two ways give bit-identical results.
+Three further measurements ride along (skipped with --no-batched / --no-diff /
+--no-djt): the batched forward of 96 float32 cubes of mixed N against
+per-volume calls; the differentiable transform (forward + backward through
+autograd) of a batch of 8 float32 N=128 cubes against per-volume forward +
+adjoint calls (both check that the two ways give bit-identical results); and
+the 3D DJT of one N=128 int32 cube, with U = 12 * 8 N^3 (N-1) voxel-stage
+updates.
 
 --copy-calibration runs only a plain 1 GiB device-to-device copy (five times),
 the reference kernel that scales the HBM byte counters.
@@ -158,6 +160,33 @@ def differentiable_speedup(api, torch, reps=5):
             "updates": U, "autograd_updates_per_s": U / (ad / 1e3)}
 
 
+def djt_rate(api, torch, reps=3):
+    """The 3D DJT of lines of one N=128 int32 cube (uniform noise in [0,3] plus
+    64 segments of value 8, seed 3) over all 12 dodecants: 4D output
+    12 x 128 x 128 x 255 x 255 (51 GB)."""
+    import workloads
+    N = 128
+    vol = torch.from_numpy(workloads.noise_with_segments(N, seed=3)).cuda()
+    out = torch.empty(api.djt3d_out_shape(N), dtype=torch.int32, device="cuda")
+    from paper_2501_13664_amd._lib import lib
+    ws = torch.empty(lib().djt3d_workspace_bytes(N, 0xFFF, 0), dtype=torch.uint8, device="cuda")
+    api.djt3d_forward(vol, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    with api.profile() as prof:
+        ms = _best_ms(torch, lambda: api.djt3d_forward(vol, out=out, workspace=ws), reps)
+    recs = prof.records
+    dom = max(recs, key=lambda k: recs[k][0])
+    dms, dn, dbytes = recs[dom]
+    achieved = (dbytes / dn) / (dms / dn / 1e3) / 1e9
+    U = 12 * 8 * N ** 3 * (N - 1)
+    return {"workload": "djt3d_forward N=128 int32, 12 dodecants, noise [0,3] + 64 segments (seed 3)",
+            "ms": ms, "updates": U, "updates_per_s": U / (ms / 1e3),
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS},
+            "kernels": {k: {"ms_total": v[0], "launches": v[1], "alg_GBps": v[2] / (v[0] / 1e3) / 1e9}
+                        for k, v in recs.items()}}
+
+
 def copy_calibration(torch):
     """Plain 1 GiB device copy, five times: the reference for the byte counters."""
     n = 1 << 28
@@ -179,6 +208,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--no-djt", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -258,6 +288,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_diff:
         line["differentiable_vs_per_volume"] = differentiable_speedup(api, torch)
+        torch.cuda.empty_cache()
+    if not args.no_djt:
+        line["djt"] = djt_rate(api, torch)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(vol_np)
