@@ -8,9 +8,10 @@
 namespace drt3d {
 
 // Affine element offset of a frame view of an N^3 volume:
-//   offset = base + sx * a + sy * b + sd * c,
-// with (a, b) the two in-plane primed coordinates and c the third one (the
-// displacement for the DRT, the driving coordinate for the DJT).
+//   offset = base + sx * a + sy * b + sd * c.
+// DRT: (a, b, c) = (x', y', N-1-z'), the stage-0 column in displacement
+// orientation; DJT: (a, b, c) = (N-1-x', N-1-y', z'), the plane in intercept
+// orientation and the driving coordinate.
 // N <= 1024 keeps every term inside int32.
 struct FrameMap {
     int base, sx, sy, sd;

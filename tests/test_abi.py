@@ -1,0 +1,170 @@
+"""The C ABI on the host (no GPU): the library loads, exports every symbol the
+header declares, answers the host-only queries, and rejects bad arguments with
+the documented status before touching a device. The frame maps it plans with
+are checked against the oracle's frames."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "drt3d.h")
+
+OK, EINVAL, ENOMEM = 0, -1, -2
+
+
+def _lib():
+    from paper_2501_13664_amd._lib import lib
+    return lib()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:drt3d|djt3d)_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for must in ("drt3d_forward", "djt3d_forward", "drt3d_adjoint", "drt3d_forward_batched",
+                 "djt3d_forward_batched", "drt3d_adjoint_batched", "drt3d_workspace_bytes",
+                 "drt3d_out_elems", "djt3d_out_elems", "drt3d_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2501_13664_amd._lib import LIB_PATH, SIGNATURES
+    names = _declared()
+    L = _lib()
+    for nm in names:
+        assert hasattr(L, nm), nm
+        assert nm in SIGNATURES, "binding lacks " + nm
+    dyn = subprocess.run(["nm", "-D", "--defined-only", LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(line.split()[-1] for line in dyn.splitlines() if line.strip())
+    assert set(names) <= exported
+
+
+def test_abi_version_and_size_queries():
+    L = _lib()
+    assert L.drt3d_abi_version() == 1
+    for N in (2, 8, 64, 512):
+        for mask in (0xFFF, 0x001, 0b101010101010):
+            k = bin(mask).count("1")
+            assert L.drt3d_out_elems(N, mask) == k * N * N * (3 * N - 2)
+            assert L.djt3d_out_elems(N, mask) == k * N * N * (2 * N - 1) ** 2
+            for dt in (0, 1):
+                assert L.drt3d_workspace_bytes(N, mask, dt) > 0
+                assert L.drt3d_adjoint_workspace_bytes(N, mask, dt) > 0
+                assert L.djt3d_workspace_bytes(N, mask, dt) > 0
+    for bad in ((3, 0xFFF), (1, 0xFFF), (0, 0xFFF), (2048, 0xFFF), (8, 0), (8, 0x1000)):
+        assert L.drt3d_out_elems(*bad) == 0
+        assert L.djt3d_out_elems(*bad) == 0
+        assert L.drt3d_workspace_bytes(bad[0], bad[1], 0) == 0
+    assert L.drt3d_workspace_bytes(8, 0xFFF, 7) == 0
+
+
+def _fake(addr):
+    return ctypes.c_void_p(addr)
+
+
+def test_bad_arguments_are_rejected_before_any_device_work():
+    L = _lib()
+    A = _fake(1 << 20)  # aligned, never dereferenced: validation fails first
+    ws_need = L.drt3d_workspace_bytes(8, 0xFFF, 0)
+    cases = [
+        (lambda: L.drt3d_forward(None, A, 8, 0xFFF, 0, A, ws_need, None), EINVAL, "NULL"),
+        (lambda: L.drt3d_forward(A, None, 8, 0xFFF, 0, A, ws_need, None), EINVAL, "NULL"),
+        (lambda: L.drt3d_forward(A, A, 6, 0xFFF, 0, A, ws_need, None), EINVAL, "power of two"),
+        (lambda: L.drt3d_forward(A, A, 1, 0xFFF, 0, A, ws_need, None), EINVAL, "power of two"),
+        (lambda: L.drt3d_forward(A, A, 8, 0, 0, A, ws_need, None), EINVAL, "mask"),
+        (lambda: L.drt3d_forward(A, A, 8, 0x1001, 0, A, ws_need, None), EINVAL, "mask"),
+        (lambda: L.drt3d_forward(A, A, 8, 0xFFF, 5, A, ws_need, None), EINVAL, "dtype"),
+        (lambda: L.drt3d_forward(_fake((1 << 20) + 4), A, 8, 0xFFF, 0, A, ws_need, None), EINVAL, "aligned"),
+        (lambda: L.drt3d_forward(A, A, 8, 0xFFF, 0, None, ws_need, None), EINVAL, "workspace"),
+        (lambda: L.drt3d_forward(A, A, 8, 0xFFF, 0, _fake((1 << 20) + 64), ws_need, None), EINVAL, "256"),
+        (lambda: L.drt3d_forward(A, A, 8, 0xFFF, 0, A, ws_need - 1, None), ENOMEM, "smaller"),
+        (lambda: L.drt3d_adjoint(A, A, 8, 0xFFF, 0, A, 16, None), ENOMEM, "smaller"),
+        (lambda: L.djt3d_forward(A, A, 8, 0xFFF, 0, A, 16, None), ENOMEM, "smaller"),
+        (lambda: L.djt3d_forward(A, A, 12, 0xFFF, 0, A, 1 << 30, None), EINVAL, "power of two"),
+    ]
+    for fn, code, word in cases:
+        assert fn() == code
+        assert word in L.drt3d_last_error().decode()
+
+
+def test_batched_argument_checks():
+    L = _lib()
+    A = (1 << 20)
+    arr = (ctypes.c_void_p * 2)(A, A)
+    Ns = (ctypes.c_int * 2)(8, 16)
+    bad_Ns = (ctypes.c_int * 2)(8, 24)
+    assert L.drt3d_forward_batched_workspace_bytes(2, Ns, 0xFFF, 0) > 0
+    assert L.drt3d_forward_batched_workspace_bytes(2, bad_Ns, 0xFFF, 0) == 0
+    assert L.drt3d_forward_batched_workspace_bytes(0, Ns, 0xFFF, 0) == 0
+    assert L.drt3d_forward_batched(0, arr, arr, Ns, 0xFFF, 0, _fake(A), 1 << 30, None) == EINVAL
+    assert L.drt3d_forward_batched(2, None, arr, Ns, 0xFFF, 0, _fake(A), 1 << 30, None) == EINVAL
+    assert L.drt3d_forward_batched(2, arr, arr, bad_Ns, 0xFFF, 0, _fake(A), 1 << 30, None) == EINVAL
+    assert L.drt3d_adjoint_batched(2, arr, arr, Ns, 0xFFF, 0, _fake(A), 16, None) == ENOMEM
+    assert L.djt3d_forward_batched(2, arr, arr, Ns, 0, 0, _fake(A), 1 << 30, None) == EINVAL
+
+
+def test_tuning_text_round_trip_and_rejection():
+    L = _lib()
+    N, dt = 64, 1
+    default = L.drt3d_tuning_string(N, dt)
+    try:
+        assert L.drt3d_set_tuning(N, dt, b"p=2.2,2.2,2.2;lds=12288;waves=4") == OK
+        assert L.drt3d_tuning_string(N, dt) == b"p=2.2,2.2,2.2;lds=12288;waves=4"
+        for bad in (b"p=3.3;lds=18432;waves=8",       # stages do not add up to n = 6
+                    b"p=4.4,2.2;lds=1024;waves=8",    # 256 columns cannot fit 1024 elements
+                    b"garbage", b""):
+            assert L.drt3d_set_tuning(N, dt, bad) == EINVAL, bad
+        assert L.drt3d_tuning_string(N, dt) == b"p=2.2,2.2,2.2;lds=12288;waves=4"
+    finally:
+        assert L.drt3d_set_tuning(N, dt, default) == OK
+
+
+def test_plan_text_lists_the_launches():
+    L = _lib()
+    buf = ctypes.create_string_buffer(1 << 16)
+    n = L.drt3d_plan_text(0, 512, 0xFFF, 0, buf, len(buf))
+    text = buf.value.decode()
+    assert n == len(text.strip().splitlines())
+    assert text.count("transpose_in") == 2 and "drt_fwd_p" in text
+    n = L.drt3d_plan_text(1, 64, 0x00F, 1, buf, len(buf))
+    text = buf.value.decode()
+    assert "drt_adj" in text and "transpose_out" not in text  # z-normal dodecants only
+    n = L.drt3d_plan_text(2, 16, 0xFFF, 0, buf, len(buf))
+    assert n == 4 and buf.value.decode().count("djt_stage") == 4
+    assert L.drt3d_plan_text(3, 16, 0xFFF, 0, buf, len(buf)) == EINVAL
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_frame_maps_agree_with_the_oracle(oracle_mod, kind):
+    """The library's affine frame maps (offset = base + sx*a + sy*b + sd*c into
+    one of its volume layouts) address the same voxel as the oracle's frames.
+    DRT: (a, b, c) = (x', y', N-1-z'), the displacement-oriented stage-0 column;
+    DJT: (a, b, c) = (N-1-x', N-1-y', z'), the plane in intercept orientation
+    and the driving coordinate u = z'."""
+    L = _lib()
+    N = 8
+    layouts = {  # group -> index of original (x, y, z) in that layout
+        0: lambda x, y, z: (x * N + y) * N + z,
+        1: lambda x, y, z: (x * N + z) * N + y,
+        2: lambda x, y, z: (y * N + z) * N + x,
+    }
+    out = (ctypes.c_int * 5)()
+    rng = np.random.default_rng(kind)
+    for k in range(12):
+        assert L.drt3d_frame_map(k, N, kind, out) == OK
+        base, sx, sy, sd, group = list(out)
+        if kind == 1:
+            assert group == 0  # the DJT reads the caller's volume directly
+        for p in rng.integers(0, N, size=(40, 3)):
+            x, y, z = oracle_mod.frame_to_orig(k, N, p)
+            a, b, c = (p[0], p[1], N - 1 - p[2]) if kind == 0 else (N - 1 - p[0], N - 1 - p[1], p[2])
+            assert base + sx * a + sy * b + sd * c == layouts[group](x, y, z), (k, tuple(p))
+    assert L.drt3d_frame_map(12, N, 0, out) == EINVAL
