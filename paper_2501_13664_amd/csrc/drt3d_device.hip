@@ -802,79 +802,178 @@ __device__ __forceinline__ int find_desc_djt(const DjtDesc* __restrict__ descs, 
     return lo;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
-djt_stage_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg)
+// DJT pass: stages m0 .. m0+K-1 of eq. (15) fused. After them the plane of
+// output slopes (s1 * 2^K + A, s2 * 2^K + B) and block V is
+//   out[e1][e2] = sum_j c_j[e1 - s1*j - loc(j, A)][e2 - s2*j - loc(j, B)],
+// c_j the input plane of block V*2^K + j. Stage t of the pass shifts the second
+// half of each merged pair by its slope (the stage-t slope plus the new bit),
+// so block j collects s*j from the slope bits the pass inherits and loc(j, A)
+// from the bits it appends: every stage t with bit t of j set adds
+// ceil((A >> (K-1-t)) / 2), at most 2^K - 1 in all. The inherited part is
+// taken out by loading block j's tile at an origin lowered by s1*j rows and
+// s2*j columns; inside the LDS tile only the local shifts remain.
+template <int K>
+__device__ __forceinline__ int djt_loc(int j, int A)
 {
+    int s = 0;
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+        if ((j >> t) & 1) s += ((A >> (K - 1 - t)) + 1) >> 1;
+    return s;
+}
+
+// Rows of output per tile of a K-stage DJT pass: eight wavefronts each load
+// four new input rows per tile (2^K planes x T1 rows in all).
+constexpr int djt_rows_per_tile(int K) { return 32 >> K; }
+constexpr int kDjtMaxChunks = 9;  // 64-column chunks of an LDS row: E_out + 2^K - 1 <= 576
+
+template <typename T, int K>
+__global__ void __launch_bounds__(512)
+djt_pass_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg)
+{
+    constexpr int NB = 1 << K, H = NB - 1, NO = NB * NB, NWV = 8;
+    constexpr int T1 = djt_rows_per_tile(K), RPW = NB * T1 / NWV, NCC = kDjtMaxChunks;
+    constexpr int HPW = (NB * H + NWV - 1) / NWV;  // halo rows per wave
+    constexpr int OPW = NO >= NWV ? NO / NWV : 1;  // output planes per wave
+    constexpr int RSTEP = NO >= NWV ? 1 : NWV / NO;  // stride of its output rows
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int nwaves = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (long long wg = blockIdx.x; wg < total_wg; wg += gridDim.x) {
         const DjtDesc* d = descs + find_desc_djt(descs, ndesc, wg);
-        long long local = wg - d->wg_begin;
-        const int band = (int)(local % d->nbands);
-        local /= d->nbands;
+        const long long local = wg - d->wg_begin;
         const int grp = (int)(local % d->groups);
         const int slot = (int)(local / d->groups);
-
-        const int n = d->n, N = d->N, m = d->m;
-        const int Vn = N >> (m + 1);            // blocks after the stage
-        const int vp = grp % Vn;                // merged block index v'
-        const int sl = grp / Vn;                // sigma1 * 2^m + sigma2
-        const int sig1 = sl >> m, sig2 = sl & ((1 << m) - 1);
+        const int N = d->N, m0 = d->m0, P = d->P;
         const int Ein = d->E_in, Eout = d->E_out;
-        const long long pin = (long long)Ein * Ein, pout = (long long)Eout * Eout;
-        const int Vm = N >> m;
-        const long long in0 = ((long long)sl * Vm + 2 * vp) * pin;
-        const long long in1 = in0 + pin;
-        const T* src = reinterpret_cast<const T*>(d->src) + (d->src_mode ? 0 : slot * d->src_slot_stride);
-        T* dst = reinterpret_cast<T*>(d->dst) + slot * d->dst_slot_stride;
-        // children (a, b): slope pair (a + 2 sigma1, b + 2 sigma2) at stage m+1
-        const int h2 = 2 << m;
-        long long outp[4];
-#pragma unroll
-        for (int ab = 0; ab < 4; ++ab) {
-            const int a = ab >> 1, b = ab & 1;
-            outp[ab] = ((long long)((a + 2 * sig1) * h2 + (b + 2 * sig2)) * Vn + vp) * pout;
-        }
+        const int Vout = N >> (m0 + K);
+        const int V = grp % Vout;
+        const int sl = grp / Vout;
+        const int s1 = sl >> m0, s2 = sl & ((1 << m0) - 1);
+        const int R = T1 + H;                 // LDS rows per plane
+        const int cols_in = Eout + H;
+        const int ncc = (cols_in + 63) >> 6;  // load chunks per row
+        const int nco = (Eout + 63) >> 6;     // output chunks per row
+        const bool fin = d->final_stage != 0;
+        const int ntiles = d->ntiles;
+        // final tiles past the support e1 <= N-1+s1 of every output slope of
+        // the group are all zeros: no loads, no LDS
+        const int nlive = fin ? min(ntiles, (N - 1 + s1 * NB + H) / T1 + 1) : ntiles;
+
+        const T* src = reinterpret_cast<const T*>(d->src);
         const FrameMap f = d->fm[slot];
-        const int r_begin = band * d->rows_per_band;
-        const int r_end = min(Eout, r_begin + d->rows_per_band);
-        for (int e1 = r_begin + wave; e1 < r_end; e1 += nwaves) {
-            for (int e2 = lane; e2 < Eout; e2 += 64) {
-                T x0, y[4];
-                const int r0 = e1 - sig1, c0 = e2 - sig2;
-                if (d->src_mode == 0) {
-                    x0 = (e1 < Ein && e2 < Ein) ? src[in0 + (long long)e1 * Ein + e2] : zero_of<T>();
+        const long long pin = (long long)Ein * Ein;
+        const T* base = src + slot * d->src_slot_stride + (long long)sl * (N >> m0) * pin;
+        const int Elim = d->src_mode ? N : Ein;
+        // element (plane j, input row e1, column e2) of this group, 0 outside
+        auto fetch = [&](int j, int e1, int e2) -> T {
+            if ((unsigned)e1 >= (unsigned)Elim || (unsigned)e2 >= (unsigned)Elim) return zero_of<T>();
+            if (d->src_mode == 0) return base[(long long)(V * NB + j) * pin + (long long)e1 * Ein + e2];
+            // stage 0: block u is the volume slice at driving coordinate u
+            return src[f.base + (long long)f.sd * (V * NB + j) + (long long)f.sx * e1 + (long long)f.sy * e2];
+        };
+        // the T1 new rows of tile `tile`: LDS rows H..H+T1-1 of every plane
+        T v[RPW][NCC];
+        auto issue = [&](int tile) {
 #pragma unroll
-                    for (int ab = 0; ab < 4; ++ab) {
-                        const int r = r0 - (ab >> 1), c = c0 - (ab & 1);
-                        y[ab] = (r >= 0 && c >= 0 && r < Ein && c < Ein) ? src[in1 + (long long)r * Ein + c]
-                                                                       : zero_of<T>();
-                    }
-                } else {
-                    // stage 0 from the volume: block v = z'; plane position (e1, e2)
-                    const long long zb = (long long)f.sd * (2 * vp);
-                    x0 = (e1 < N && e2 < N) ? src[f.base + (long long)f.sx * e1 + (long long)f.sy * e2 + zb]
-                                            : zero_of<T>();
+            for (int i = 0; i < RPW; ++i) {
+                const int q = wave + NWV * i;          // (plane j, new row r) = (q / T1, q % T1)
+                const int j = q / T1, r = q % T1;
+                const int e1 = tile * T1 - s1 * j + r;
 #pragma unroll
-                    for (int ab = 0; ab < 4; ++ab) {
-                        const int r = r0 - (ab >> 1), c = c0 - (ab & 1);
-                        y[ab] = (r >= 0 && c >= 0 && r < N && c < N)
-                                    ? src[f.base + (long long)f.sx * r + (long long)f.sy * c + zb + f.sd]
-                                    : zero_of<T>();
+                for (int t = 0; t < NCC; ++t) {
+                    const int c = 64 * t + lane;
+                    v[i][t] = t < ncc && c < cols_in ? fetch(j, e1, c - s2 * j - H) : zero_of<T>();
+                }
+            }
+        };
+        // the output planes of this wave: LDS row bases and output bases
+        T* dst = reinterpret_cast<T*>(d->dst) + slot * d->dst_slot_stride;
+        const int Sout = 1 << (m0 + K);
+        const long long pout = (long long)Eout * Eout;
+        const int o0 = wave % (NO >= NWV ? NWV : NO);
+        const int r0w = NO >= NWV ? 0 : wave / NO;
+        int rb[OPW][NB], ot1[OPW], ocmax[OPW];
+        T* obase[OPW];
+#pragma unroll
+        for (int p = 0; p < OPW; ++p) {
+            const int o = o0 + NWV * p;
+            const int A = o >> K, B = o & H;
+            const int t1 = s1 * NB + A, t2 = s2 * NB + B;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) rb[p][j] = (j * R + H - djt_loc<K>(j, A)) * P + H - djt_loc<K>(j, B);
+            ot1[p] = t1;
+            ocmax[p] = fin ? min(Eout, N + t2) : Eout;
+            obase[p] = dst + ((long long)(t1 * Sout + t2) * Vout + V) * pout;
+        }
+        if (nlive > 0) issue(0);
+        for (int tile = 0; tile < ntiles; ++tile) {
+            const int e1_0 = tile * T1;
+            const int rows = min(T1, Eout - e1_0);
+            const bool live = tile < nlive;
+            if (live) {
+                // halo: the previous tile's top H rows (zeros for the first)
+                T h[HPW][NCC];
+#pragma unroll
+                for (int i = 0; i < HPW; ++i) {
+                    const int q = wave + NWV * i;      // (plane, halo row) = (q / H, q % H)
+#pragma unroll
+                    for (int t = 0; t < NCC; ++t) {
+                        const int c = 64 * t + lane;
+                        h[i][t] = tile > 0 && q < NB * H && t < ncc && c < cols_in
+                                      ? lds[((q / H) * R + T1 + q % H) * P + c]
+                                      : zero_of<T>();
                     }
                 }
-                const long long o = (long long)e1 * Eout + e2;
-                if (d->final_stage) {
+                __syncthreads();  // previous output phase and halo reads done
 #pragma unroll
-                    for (int ab = 0; ab < 4; ++ab) __builtin_nontemporal_store(x0 + y[ab], dst + outp[ab] + o);
-                } else {
+                for (int i = 0; i < HPW; ++i) {
+                    const int q = wave + NWV * i;
 #pragma unroll
-                    for (int ab = 0; ab < 4; ++ab) dst[outp[ab] + o] = x0 + y[ab];
+                    for (int t = 0; t < NCC; ++t) {
+                        const int c = 64 * t + lane;
+                        if (q < NB * H && t < ncc && c < cols_in) lds[((q / H) * R + q % H) * P + c] = h[i][t];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < RPW; ++i) {
+                    const int q = wave + NWV * i;
+#pragma unroll
+                    for (int t = 0; t < NCC; ++t) {
+                        const int c = 64 * t + lane;
+                        if (t < ncc && c < cols_in) lds[((q / T1) * R + H + q % T1) * P + c] = v[i][t];
+                    }
+                }
+                __syncthreads();
+                if (tile + 1 < nlive) issue(tile + 1);
+            }
+            // outputs: each wave owns planes o = o0 + NWV * p and rows
+            // r = r0 + RSTEP * i of the tile
+#pragma unroll
+            for (int p = 0; p < OPW; ++p) {
+                for (int r = r0w; r < rows; r += RSTEP) {
+                    const int e1 = e1_0 + r;
+                    T* orow = obase[p] + (long long)e1 * Eout;
+                    // final output: rows past N-1+t1 and columns past N-1+t2 are zero
+                    const int cmax = !live || (fin && e1 > N - 1 + ot1[p]) ? 0 : ocmax[p];
+#pragma unroll
+                    for (int t = 0; t < NCC; ++t) {
+                        const int c = 64 * t + lane;
+                        if (t < nco && c < Eout) {
+                            T x = zero_of<T>();
+                            if (c < cmax) {
+#pragma unroll
+                                for (int j = 0; j < NB; ++j) x += lds[rb[p][j] + r * P + c];
+                            }
+                            if (fin) __builtin_nontemporal_store(x, orow + c);
+                            else orow[c] = x;
+                        }
+                    }
                 }
             }
         }
+        __syncthreads();  // the next work item reuses the LDS
     }
 }
 
@@ -912,8 +1011,24 @@ static hipError_t set_fast_lds_limit(size_t bytes)
     return hipSuccess;
 }
 
+template <typename T>
+static const void* djt_kernel(int K)
+{
+    switch (K) {
+    case 1: return reinterpret_cast<const void*>(&djt_pass_kernel<T, 1>);
+    case 2: return reinterpret_cast<const void*>(&djt_pass_kernel<T, 2>);
+    case 3: return reinterpret_cast<const void*>(&djt_pass_kernel<T, 3>);
+    default: return nullptr;
+    }
+}
+
 hipError_t set_drt_lds_limit(int is_float, size_t bytes)
 {
+    for (int K = 1; K <= 3; ++K) {
+        hipError_t e = hipFuncSetAttribute(is_float ? djt_kernel<float>(K) : djt_kernel<uint32_t>(K),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
     {
         hipError_t e = is_float ? set_fast_lds_limit<float>(bytes) : set_fast_lds_limit<uint32_t>(bytes);
         if (e != hipSuccess) return e;
@@ -949,15 +1064,17 @@ hipError_t launch_drt_pass(int is_float, const DrtDesc* d_descs, int ndesc, long
     return hipGetLastError();
 }
 
-hipError_t launch_djt_stage(int is_float, const DjtDesc* d_descs, int ndesc, long long total_wg,
-                            int block, int grid, hipStream_t s)
+hipError_t launch_djt_pass(int is_float, int K, const DjtDesc* d_descs, int ndesc, long long total_wg, int grid,
+                           size_t lds_bytes, hipStream_t s)
 {
-    if (is_float)
-        hipLaunchKernelGGL(djt_stage_kernel<float>, dim3(grid), dim3(block), 0, s, d_descs, ndesc, total_wg);
-    else
-        hipLaunchKernelGGL(djt_stage_kernel<uint32_t>, dim3(grid), dim3(block), 0, s, d_descs, ndesc, total_wg);
-    return hipGetLastError();
+    const void* k = is_float ? djt_kernel<float>(K) : djt_kernel<uint32_t>(K);
+    if (!k) return hipErrorInvalidValue;
+    void* args[] = {&d_descs, &ndesc, &total_wg};
+    return hipLaunchKernel(k, dim3(grid), dim3(512), args, lds_bytes, s);
 }
+
+int djt_tile_rows(int K) { return djt_rows_per_tile(K); }
+int djt_max_lds_cols() { return 64 * kDjtMaxChunks; }
 
 hipError_t launch_transpose(int is_float, const TransDesc* d_descs, int ndesc, long long total_wg,
                             hipStream_t s)

@@ -44,18 +44,24 @@ struct DrtDesc {
     FrameMap fm[kMaxSlots];
 };
 
-// One DJT stage m -> m+1 of eq. (15) for every (block pair, slope pair) group
-// of every dodecant slot. Work items are (slot, group, row band) flattened.
+// One DJT pass: stages m0 .. m0+K-1 of eq. (15) fused, for every group of
+// every dodecant slot. A group is a slope pair (s1, s2) of stage m0 and the
+// 2^K blocks it merges into one block V of stage m0+K; it reads 2^K planes and
+// writes 4^K. Planes are E x E, row-major in (e1, e2); buffers are
+// [s1 * 2^m + s2][block][e1][e2] (the final output: [s1][s2][e1][e2]). Work
+// items are (slot, group) flattened; each runs over its tiles of T1 output
+// rows in order.
 struct DjtDesc {
     long long wg_begin;
-    long long src_slot_stride, dst_slot_stride;
+    long long src_slot_stride, dst_slot_stride;  // elements between slots
     const void* src;  // stage buffer, or the volume when src_mode == 1
     void* dst;
-    int groups, nbands, rows_per_band, nslots;
-    int N, n, m;
-    int E_in, E_out;  // square plane extents (row pitch == extent)
+    int groups, ntiles, T1, nslots;
+    int N, n, m0, K;
+    int E_in, E_out;  // plane extents before and after the pass
+    int P;            // LDS row pitch (>= E_out + 2^K - 1)
     int src_mode;
-    int final_stage;  // output is the caller's buffer: stream past the caches
+    int final_stage;  // output is the caller's buffer: zero tails skipped, streamed past the caches
     FrameMap fm[kMaxSlots];
 };
 
@@ -73,8 +79,12 @@ struct TransDesc {
 // Launchers (device code translation unit).
 hipError_t launch_drt_pass(int is_float, const DrtDesc* d_descs, int ndesc, long long total_wg,
                            int block, int grid, size_t lds_bytes, hipStream_t s);
-hipError_t launch_djt_stage(int is_float, const DjtDesc* d_descs, int ndesc, long long total_wg,
-                            int block, int grid, hipStream_t s);
+// Output rows per tile of a K-stage DJT pass, and the longest LDS row
+// (E_out + 2^K - 1) the pass kernels take.
+int djt_tile_rows(int K);
+int djt_max_lds_cols();
+hipError_t launch_djt_pass(int is_float, int K, const DjtDesc* d_descs, int ndesc, long long total_wg, int grid,
+                           size_t lds_bytes, hipStream_t s);
 hipError_t launch_transpose(int is_float, const TransDesc* d_descs, int ndesc, long long total_wg,
                             hipStream_t s);
 hipError_t set_drt_lds_limit(int is_float, size_t bytes);

@@ -394,6 +394,7 @@ struct Launch {
     std::string name;
     int fast_kx = -1, fast_ky = -1, fast_nch = -1;  // shape-specialised DRT kernel, if any
     int fast_final = 0;                             // ... its forward-last-pass form
+    int djt_k = 0;                                  // DJT: stages fused per pass
     int first = 0, ndesc = 0;
     long long total_wg = 0;
     int persistent = 0;  // grid capped at a few work groups per CU, looping over the items
@@ -493,8 +494,9 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
             } else {
                 for (DjtDesc d : s->djt) {
                     d.wg_begin = wg;
-                    wg += (long long)d.nslots * d.groups * d.nbands;
+                    wg += (long long)d.nslots * d.groups;
                     prog.djt.push_back(d);
+                    L.djt_k = d.K;
                 }
             }
         }
@@ -599,8 +601,11 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
                 e = launch_drt_pass(p.is_float, d_drt + L.first, L.ndesc, L.total_wg, L.block,
                                     grid_for(L.total_wg, di, L.persistent), L.lds, s);
         } else if (L.kind == S_DJT) {
-            e = launch_djt_stage(p.is_float, d_djt + L.first, L.ndesc, L.total_wg, L.block,
-                                 grid_for(L.total_wg, di, L.persistent), s);
+            if (L.lds > (size_t)di.max_lds)
+                return fail(DRT3D_EINVAL, "%s needs %zu bytes of LDS, the device allows %d", L.name.c_str(), L.lds,
+                            di.max_lds);
+            e = launch_djt_pass(p.is_float, L.djt_k, d_djt + L.first, L.ndesc, L.total_wg,
+                                grid_for(L.total_wg, di, L.persistent), L.lds, s);
         } else {
             e = launch_transpose(p.is_float, d_tr + L.first, L.ndesc, L.total_wg, s);
         }
@@ -891,20 +896,41 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
 // ------------------------------------------------------------------ DJT plan
 static long long djt_extent(int N, int m) { return (long long)N + (1LL << m) - 1; }
 
-// Elements of the stage-m -> m+1 output of one dodecant (m < n-1).
-static long long djt_stage_out_elems(int N, int m)
+// Stages per DJT pass, in order: the last pass fuses 2 stages (its 4^K output
+// planes per group are the large ones), the earlier ones up to 3.
+static std::vector<int> djt_plan(int n)
 {
-    const long long E = djt_extent(N, m + 1);
-    return (long long)N * (2LL << m) * E * E;
+    std::vector<int> ks;
+    const int last = std::min(2, n);
+    int rest = n - last;
+    while (rest > 0) {
+        const int k = std::min(3, rest);
+        ks.push_back(k);
+        rest -= k;
+    }
+    ks.push_back(last);
+    return ks;
 }
 
+// Elements of one dodecant's stage-m buffer (2^m slope pairs of N >> m blocks
+// ... = N * 2^m planes of E_m x E_m).
+static long long djt_stage_elems(int N, int m)
+{
+    const long long E = djt_extent(N, m);
+    return (long long)N * (1LL << m) * E * E;
+}
+
+// Ping-pong buffer sizes (elements per dodecant) for the outputs of every
+// pass but the last.
 static void djt_buffer_elems(int N, long long& a, long long& b)
 {
-    const int n = ilog2_exact(N);
+    const std::vector<int> ks = djt_plan(ilog2_exact(N));
     a = 0; b = 0;
-    for (int m = 0; m + 1 < n; ++m) {
-        const long long e = djt_stage_out_elems(N, m);
-        if (m & 1) b = std::max(b, e); else a = std::max(a, e);
+    int m = 0;
+    for (size_t i = 0; i + 1 < ks.size(); ++i) {
+        m += ks[i];
+        const long long e = djt_stage_elems(N, m);
+        if (i & 1) b = std::max(b, e); else a = std::max(a, e);
     }
 }
 
@@ -932,37 +958,50 @@ static int djt_steps(std::vector<Step>& steps, int N, uint32_t mask, int chunked
     void* buf[2];
     buf[0] = w; w += align256((size_t)chunk * A * elem);
     buf[1] = w;
+    const std::vector<int> ks = djt_plan(n);
+    const int np = (int)ks.size();
     const long long Ef = 2LL * N - 1;
     const long long slot_out = (long long)N * N * Ef * Ef;
     for (int c0 = 0; c0 < nd; c0 += chunk) {
         const int ns = std::min(chunk, nd - c0);
-        for (int m = 0; m < n; ++m) {
+        int m0 = 0;
+        for (int i = 0; i < np; ++i) {
+            const int K = ks[i];
+            const int NB = 1 << K, H = NB - 1;
             DjtDesc d{};
-            d.N = N; d.n = n; d.m = m;
-            d.E_in = (int)djt_extent(N, m);
-            d.E_out = (int)djt_extent(N, m + 1);
-            d.groups = (N >> (m + 1)) << (2 * m);
-            d.rows_per_band = 16;
-            d.nbands = (d.E_out + d.rows_per_band - 1) / d.rows_per_band;
+            d.N = N; d.n = n; d.m0 = m0; d.K = K;
+            d.E_in = (int)djt_extent(N, m0);
+            d.E_out = (int)djt_extent(N, m0 + K);
+            d.P = d.E_out + H;
+            if (d.P > djt_max_lds_cols())
+                return fail(DRT3D_EUNSUPPORTED, "the DJT is built for N <= 256 (got N = %d)", N);
+            d.T1 = djt_tile_rows(K);
+            d.ntiles = (d.E_out + d.T1 - 1) / d.T1;
+            d.groups = (1 << (2 * m0)) * (N >> (m0 + K));
             d.nslots = ns;
             for (int s = 0; s < ns; ++s) d.fm[s] = djt_frame_map(dods[c0 + s], N);
-            if (m == 0) { d.src_mode = 1; d.src = io.in; }
-            else { d.src = buf[(m - 1) & 1]; d.src_slot_stride = (m - 1) & 1 ? B : A; }
-            if (m == n - 1) {
+            if (i == 0) { d.src_mode = 1; d.src = io.in; }
+            else { d.src = buf[(i - 1) & 1]; d.src_slot_stride = (i - 1) & 1 ? B : A; }
+            if (i == np - 1) {
                 d.dst = (char*)io.out + (size_t)c0 * slot_out * elem;
                 d.dst_slot_stride = slot_out;
                 d.final_stage = 1;
             } else {
-                d.dst = buf[m & 1];
-                d.dst_slot_stride = m & 1 ? B : A;
+                d.dst = buf[i & 1];
+                d.dst_slot_stride = i & 1 ? B : A;
             }
-            Step s; s.kind = S_DJT; s.key = kKeyPass + m; s.name = m == n - 1 ? "djt_stage_last" : "djt_stage";
-            s.waves = 4;
-            const double in_e = m == 0 ? (double)N * N * N : (double)N * (1LL << m) * d.E_in * d.E_in;
-            const double out_e = (double)N * (2LL << m) * d.E_out * d.E_out;
+            char nm[32];
+            snprintf(nm, sizeof nm, "djt_p%d", i + 1);
+            Step s; s.kind = S_DJT; s.key = kKeyPass + i; s.name = nm;
+            s.waves = 8;
+            s.shape = K;
+            s.lds = (size_t)NB * (d.T1 + H) * d.P * elem;
+            const double in_e = i == 0 ? (double)N * N * N : (double)djt_stage_elems(N, m0);
+            const double out_e = (double)djt_stage_elems(N, m0 + K);
             s.bytes = (double)ns * elem * (in_e + out_e);
             s.djt.push_back(d);
             steps.push_back(s);
+            m0 += K;
         }
     }
     return DRT3D_OK;
