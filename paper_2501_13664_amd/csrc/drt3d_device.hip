@@ -825,16 +825,18 @@ __device__ __forceinline__ int djt_loc(int j, int A)
 // Rows of output per tile of a K-stage DJT pass: eight wavefronts each load
 // four new input rows per tile (2^K planes x T1 rows in all).
 constexpr int djt_rows_per_tile(int K) { return 32 >> K; }
-constexpr int kDjtMaxChunks = 9;  // 64-column chunks of an LDS row: E_out + 2^K - 1 <= 576
+// 64-column chunks of an LDS row (E_out + 2^K - 1 columns), one kernel per
+// count; the largest takes N = 256.
+constexpr int kDjtChunkCounts[] = {1, 2, 3, 5, 9};
 
-template <typename T, int K>
+template <typename T, int K, int NCC>
 __global__ void __launch_bounds__(512)
 djt_pass_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg)
 {
     constexpr int NB = 1 << K, H = NB - 1, NO = NB * NB, NWV = 8;
-    constexpr int T1 = djt_rows_per_tile(K), RPW = NB * T1 / NWV, NCC = kDjtMaxChunks;
-    constexpr int HPW = (NB * H + NWV - 1) / NWV;  // halo rows per wave
-    constexpr int OPW = NO >= NWV ? NO / NWV : 1;  // output planes per wave
+    constexpr int T1 = djt_rows_per_tile(K), RPW = NB * T1 / NWV;
+    constexpr int HPW = (NB * H + NWV - 1) / NWV;    // halo rows per wave
+    constexpr int OPW = NO >= NWV ? NO / NWV : 1;    // output planes per wave
     constexpr int RSTEP = NO >= NWV ? 1 : NWV / NO;  // stride of its output rows
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
@@ -853,7 +855,6 @@ djt_pass_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg
         const int s1 = sl >> m0, s2 = sl & ((1 << m0) - 1);
         const int R = T1 + H;                 // LDS rows per plane
         const int cols_in = Eout + H;
-        const int ncc = (cols_in + 63) >> 6;  // load chunks per row
         const int nco = (Eout + 63) >> 6;     // output chunks per row
         const bool fin = d->final_stage != 0;
         const int ntiles = d->ntiles;
@@ -861,52 +862,51 @@ djt_pass_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg
         // the group are all zeros: no loads, no LDS
         const int nlive = fin ? min(ntiles, (N - 1 + s1 * NB + H) / T1 + 1) : ntiles;
 
-        const T* src = reinterpret_cast<const T*>(d->src);
-        const FrameMap f = d->fm[slot];
-        const long long pin = (long long)Ein * Ein;
-        const T* base = src + slot * d->src_slot_stride + (long long)sl * (N >> m0) * pin;
-        const int Elim = d->src_mode ? N : Ein;
-        // element (plane j, input row e1, column e2) of this group, 0 outside
-        auto fetch = [&](int j, int e1, int e2) -> T {
-            if ((unsigned)e1 >= (unsigned)Elim || (unsigned)e2 >= (unsigned)Elim) return zero_of<T>();
-            if (d->src_mode == 0) return base[(long long)(V * NB + j) * pin + (long long)e1 * Ein + e2];
-            // stage 0: block u is the volume slice at driving coordinate u
-            return src[f.base + (long long)f.sd * (V * NB + j) + (long long)f.sx * e1 + (long long)f.sy * e2];
-        };
+        // input: the group's 2^K planes are consecutive in the stage buffer;
+        // stage 0 reads the volume through the frame map. Out-of-range lanes
+        // get an offset past the resource: the hardware returns 0.
+        __amdgpu_buffer_rsrc_t rs_in;
+        int ib, isx, isy, isd, Elim;
+        if (d->src_mode == 0) {
+            const long long pin = (long long)Ein * Ein;
+            const T* base = reinterpret_cast<const T*>(d->src) + slot * d->src_slot_stride +
+                            ((long long)sl * (N >> m0) + (long long)V * NB) * pin;
+            rs_in = make_rsrc(base, (int)(NB * pin));
+            ib = 0; isx = Ein; isy = 1; isd = (int)pin; Elim = Ein;
+        } else {
+            const FrameMap f = d->fm[slot];
+            rs_in = make_rsrc(reinterpret_cast<const T*>(d->src), N * N * N);
+            ib = f.base + f.sd * V * NB; isx = f.sx; isy = f.sy; isd = f.sd; Elim = N;
+        }
+        // output: the group's planes (t1, t2) = (s1*2^K + A, s2*2^K + B) lie
+        // inside 2^K runs of 2^K planes, Sout planes apart
+        const int Sout = 1 << (m0 + K);
+        const int pout = Eout * Eout;
+        const __amdgpu_buffer_rsrc_t rs_out = make_rsrc(
+            reinterpret_cast<T*>(d->dst) + slot * d->dst_slot_stride +
+                ((long long)(s1 * NB * Sout + s2 * NB) * Vout + V) * pout,
+            ((H * Sout + NB - 1) * Vout + 1) * pout);
+        const int o0 = wave % (NO >= NWV ? NWV : NO);
+        const int r0w = NO >= NWV ? 0 : wave / NO;
+
+        uint32_t v[RPW][NCC];
         // the T1 new rows of tile `tile`: LDS rows H..H+T1-1 of every plane
-        T v[RPW][NCC];
         auto issue = [&](int tile) {
 #pragma unroll
             for (int i = 0; i < RPW; ++i) {
-                const int q = wave + NWV * i;          // (plane j, new row r) = (q / T1, q % T1)
+                const int q = wave + NWV * i;  // (plane j, new row r) = (q / T1, q % T1)
                 const int j = q / T1, r = q % T1;
                 const int e1 = tile * T1 - s1 * j + r;
+                const bool rin = (unsigned)e1 < (unsigned)Elim;
+                const int rowb = ib + isd * j + isx * e1;
 #pragma unroll
                 for (int t = 0; t < NCC; ++t) {
-                    const int c = 64 * t + lane;
-                    v[i][t] = t < ncc && c < cols_in ? fetch(j, e1, c - s2 * j - H) : zero_of<T>();
+                    const int e2 = 64 * t + lane - s2 * j - H;
+                    const bool in = rin && (unsigned)e2 < (unsigned)Elim;
+                    v[i][t] = bload(rs_in, in ? 4 * (rowb + isy * e2) : -1);
                 }
             }
         };
-        // the output planes of this wave: LDS row bases and output bases
-        T* dst = reinterpret_cast<T*>(d->dst) + slot * d->dst_slot_stride;
-        const int Sout = 1 << (m0 + K);
-        const long long pout = (long long)Eout * Eout;
-        const int o0 = wave % (NO >= NWV ? NWV : NO);
-        const int r0w = NO >= NWV ? 0 : wave / NO;
-        int rb[OPW][NB], ot1[OPW], ocmax[OPW];
-        T* obase[OPW];
-#pragma unroll
-        for (int p = 0; p < OPW; ++p) {
-            const int o = o0 + NWV * p;
-            const int A = o >> K, B = o & H;
-            const int t1 = s1 * NB + A, t2 = s2 * NB + B;
-#pragma unroll
-            for (int j = 0; j < NB; ++j) rb[p][j] = (j * R + H - djt_loc<K>(j, A)) * P + H - djt_loc<K>(j, B);
-            ot1[p] = t1;
-            ocmax[p] = fin ? min(Eout, N + t2) : Eout;
-            obase[p] = dst + ((long long)(t1 * Sout + t2) * Vout + V) * pout;
-        }
         if (nlive > 0) issue(0);
         for (int tile = 0; tile < ntiles; ++tile) {
             const int e1_0 = tile * T1;
@@ -914,16 +914,16 @@ djt_pass_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg
             const bool live = tile < nlive;
             if (live) {
                 // halo: the previous tile's top H rows (zeros for the first)
-                T h[HPW][NCC];
+                uint32_t h[HPW][NCC];
 #pragma unroll
                 for (int i = 0; i < HPW; ++i) {
-                    const int q = wave + NWV * i;      // (plane, halo row) = (q / H, q % H)
+                    const int q = wave + NWV * i;  // (plane, halo row) = (q / H, q % H)
 #pragma unroll
                     for (int t = 0; t < NCC; ++t) {
                         const int c = 64 * t + lane;
-                        h[i][t] = tile > 0 && q < NB * H && t < ncc && c < cols_in
-                                      ? lds[((q / H) * R + T1 + q % H) * P + c]
-                                      : zero_of<T>();
+                        h[i][t] = tile > 0 && q < NB * H && c < cols_in
+                                      ? to_bits(lds[((q / H) * R + T1 + q % H) * P + c])
+                                      : 0u;
                     }
                 }
                 __syncthreads();  // previous output phase and halo reads done
@@ -933,7 +933,7 @@ djt_pass_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg
 #pragma unroll
                     for (int t = 0; t < NCC; ++t) {
                         const int c = 64 * t + lane;
-                        if (q < NB * H && t < ncc && c < cols_in) lds[((q / H) * R + q % H) * P + c] = h[i][t];
+                        if (q < NB * H && c < cols_in) lds[((q / H) * R + q % H) * P + c] = from_bits<T>(h[i][t]);
                     }
                 }
 #pragma unroll
@@ -942,33 +942,45 @@ djt_pass_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg
 #pragma unroll
                     for (int t = 0; t < NCC; ++t) {
                         const int c = 64 * t + lane;
-                        if (t < ncc && c < cols_in) lds[((q / T1) * R + H + q % T1) * P + c] = v[i][t];
+                        if (c < cols_in) lds[((q / T1) * R + H + q % T1) * P + c] = from_bits<T>(v[i][t]);
                     }
                 }
                 __syncthreads();
-                if (tile + 1 < nlive) issue(tile + 1);
             }
             // outputs: each wave owns planes o = o0 + NWV * p and rows
-            // r = r0 + RSTEP * i of the tile
+            // r = r0 + RSTEP * i of the tile. The loop is unrolled with every
+            // store unconditional (lanes past a row or past the last row get
+            // an offset outside the resource), so the next tile's loads can be
+            // issued half way through and waited for with the later half of
+            // the stores still in flight.
+            constexpr int RPWO = T1 / RSTEP;  // output rows per wave per plane
 #pragma unroll
             for (int p = 0; p < OPW; ++p) {
-                for (int r = r0w; r < rows; r += RSTEP) {
+                const int o = o0 + NWV * p;
+                const int A = o >> K, B = o & H;
+                const int t1 = s1 * NB + A;
+                const int pb = (A * Sout + B) * Vout * pout;  // plane offset inside rs_out
+                const int ccap = fin ? min(Eout, N + s2 * NB + B) : Eout;
+                int lb[NB];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) lb[j] = (j * R + H - djt_loc<K>(j, A)) * P + H - djt_loc<K>(j, B);
+#pragma unroll
+                for (int i = 0; i < RPWO; ++i) {
+                    if (p * RPWO + i == (OPW * RPWO) / 2 && live && tile + 1 < nlive) issue(tile + 1);
+                    const int r = r0w + RSTEP * i;
                     const int e1 = e1_0 + r;
-                    T* orow = obase[p] + (long long)e1 * Eout;
                     // final output: rows past N-1+t1 and columns past N-1+t2 are zero
-                    const int cmax = !live || (fin && e1 > N - 1 + ot1[p]) ? 0 : ocmax[p];
+                    const int cmax = !live || r >= rows || (fin && e1 > N - 1 + t1) ? 0 : ccap;
+                    const int ob = r < rows ? pb + e1 * Eout : -(1 << 30);
 #pragma unroll
                     for (int t = 0; t < NCC; ++t) {
                         const int c = 64 * t + lane;
-                        if (t < nco && c < Eout) {
-                            T x = zero_of<T>();
-                            if (c < cmax) {
+                        T x = zero_of<T>();
+                        if (c < cmax) {
 #pragma unroll
-                                for (int j = 0; j < NB; ++j) x += lds[rb[p][j] + r * P + c];
-                            }
-                            if (fin) __builtin_nontemporal_store(x, orow + c);
-                            else orow[c] = x;
+                            for (int j = 0; j < NB; ++j) x += lds[lb[j] + r * P + c];
                         }
+                        bstore(rs_out, c < Eout && ob >= 0 ? 4 * (ob + c) : -1, to_bits(x));
                     }
                 }
             }
@@ -1011,24 +1023,38 @@ static hipError_t set_fast_lds_limit(size_t bytes)
     return hipSuccess;
 }
 
+template <typename T, int K>
+static const void* djt_kernel_k(int ncc)
+{
+    switch (ncc) {
+    case 1: return reinterpret_cast<const void*>(&djt_pass_kernel<T, K, 1>);
+    case 2: return reinterpret_cast<const void*>(&djt_pass_kernel<T, K, 2>);
+    case 3: return reinterpret_cast<const void*>(&djt_pass_kernel<T, K, 3>);
+    case 5: return reinterpret_cast<const void*>(&djt_pass_kernel<T, K, 5>);
+    case 9: return reinterpret_cast<const void*>(&djt_pass_kernel<T, K, 9>);
+    default: return nullptr;
+    }
+}
+
 template <typename T>
-static const void* djt_kernel(int K)
+static const void* djt_kernel(int K, int ncc)
 {
     switch (K) {
-    case 1: return reinterpret_cast<const void*>(&djt_pass_kernel<T, 1>);
-    case 2: return reinterpret_cast<const void*>(&djt_pass_kernel<T, 2>);
-    case 3: return reinterpret_cast<const void*>(&djt_pass_kernel<T, 3>);
+    case 1: return djt_kernel_k<T, 1>(ncc);
+    case 2: return djt_kernel_k<T, 2>(ncc);
+    case 3: return djt_kernel_k<T, 3>(ncc);
     default: return nullptr;
     }
 }
 
 hipError_t set_drt_lds_limit(int is_float, size_t bytes)
 {
-    for (int K = 1; K <= 3; ++K) {
-        hipError_t e = hipFuncSetAttribute(is_float ? djt_kernel<float>(K) : djt_kernel<uint32_t>(K),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-    }
+    for (int K = 1; K <= 3; ++K)
+        for (int ncc : kDjtChunkCounts) {
+            hipError_t e = hipFuncSetAttribute(is_float ? djt_kernel<float>(K, ncc) : djt_kernel<uint32_t>(K, ncc),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+            if (e != hipSuccess) return e;
+        }
     {
         hipError_t e = is_float ? set_fast_lds_limit<float>(bytes) : set_fast_lds_limit<uint32_t>(bytes);
         if (e != hipSuccess) return e;
@@ -1064,17 +1090,23 @@ hipError_t launch_drt_pass(int is_float, const DrtDesc* d_descs, int ndesc, long
     return hipGetLastError();
 }
 
-hipError_t launch_djt_pass(int is_float, int K, const DjtDesc* d_descs, int ndesc, long long total_wg, int grid,
-                           size_t lds_bytes, hipStream_t s)
+hipError_t launch_djt_pass(int is_float, int K, int ncc, const DjtDesc* d_descs, int ndesc, long long total_wg,
+                           int grid, size_t lds_bytes, hipStream_t s)
 {
-    const void* k = is_float ? djt_kernel<float>(K) : djt_kernel<uint32_t>(K);
+    const void* k = is_float ? djt_kernel<float>(K, ncc) : djt_kernel<uint32_t>(K, ncc);
     if (!k) return hipErrorInvalidValue;
     void* args[] = {&d_descs, &ndesc, &total_wg};
     return hipLaunchKernel(k, dim3(grid), dim3(512), args, lds_bytes, s);
 }
 
 int djt_tile_rows(int K) { return djt_rows_per_tile(K); }
-int djt_max_lds_cols() { return 64 * kDjtMaxChunks; }
+
+int djt_chunks_for(int cols)
+{
+    for (int ncc : kDjtChunkCounts)
+        if (64 * ncc >= cols) return ncc;
+    return 0;
+}
 
 hipError_t launch_transpose(int is_float, const TransDesc* d_descs, int ndesc, long long total_wg,
                             hipStream_t s)

@@ -79,12 +79,12 @@ struct TransDesc {
 // Launchers (device code translation unit).
 hipError_t launch_drt_pass(int is_float, const DrtDesc* d_descs, int ndesc, long long total_wg,
                            int block, int grid, size_t lds_bytes, hipStream_t s);
-// Output rows per tile of a K-stage DJT pass, and the longest LDS row
-// (E_out + 2^K - 1) the pass kernels take.
+// Output rows per tile of a K-stage DJT pass, and the 64-column chunk count
+// of the kernel that takes LDS rows of `cols` columns (0: none does).
 int djt_tile_rows(int K);
-int djt_max_lds_cols();
-hipError_t launch_djt_pass(int is_float, int K, const DjtDesc* d_descs, int ndesc, long long total_wg, int grid,
-                           size_t lds_bytes, hipStream_t s);
+int djt_chunks_for(int cols);
+hipError_t launch_djt_pass(int is_float, int K, int ncc, const DjtDesc* d_descs, int ndesc, long long total_wg,
+                           int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_transpose(int is_float, const TransDesc* d_descs, int ndesc, long long total_wg,
                             hipStream_t s);
 hipError_t set_drt_lds_limit(int is_float, size_t bytes);

@@ -394,7 +394,7 @@ struct Launch {
     std::string name;
     int fast_kx = -1, fast_ky = -1, fast_nch = -1;  // shape-specialised DRT kernel, if any
     int fast_final = 0;                             // ... its forward-last-pass form
-    int djt_k = 0;                                  // DJT: stages fused per pass
+    int djt_k = 0, djt_ncc = 0;                     // DJT: stages fused per pass, LDS row chunks
     int first = 0, ndesc = 0;
     long long total_wg = 0;
     int persistent = 0;  // grid capped at a few work groups per CU, looping over the items
@@ -497,6 +497,7 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
                     wg += (long long)d.nslots * d.groups;
                     prog.djt.push_back(d);
                     L.djt_k = d.K;
+                    L.djt_ncc = s->shape >> 4;
                 }
             }
         }
@@ -604,7 +605,7 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
             if (L.lds > (size_t)di.max_lds)
                 return fail(DRT3D_EINVAL, "%s needs %zu bytes of LDS, the device allows %d", L.name.c_str(), L.lds,
                             di.max_lds);
-            e = launch_djt_pass(p.is_float, L.djt_k, d_djt + L.first, L.ndesc, L.total_wg,
+            e = launch_djt_pass(p.is_float, L.djt_k, L.djt_ncc, d_djt + L.first, L.ndesc, L.total_wg,
                                 grid_for(L.total_wg, di, L.persistent), L.lds, s);
         } else {
             e = launch_transpose(p.is_float, d_tr + L.first, L.ndesc, L.total_wg, s);
@@ -901,6 +902,19 @@ static long long djt_extent(int N, int m) { return (long long)N + (1LL << m) - 1
 static std::vector<int> djt_plan(int n)
 {
     std::vector<int> ks;
+    // DRT3D_DJT_PASSES="k1,k2,..." (each 1..3, summing to n) overrides the rule
+    if (const char* env = getenv("DRT3D_DJT_PASSES")) {
+        int sum = 0;
+        bool ok = true;
+        for (const char* p = env; *p; ++p) {
+            if (*p == ',') continue;
+            if (*p < '1' || *p > '3') { ok = false; break; }
+            ks.push_back(*p - '0');
+            sum += *p - '0';
+        }
+        if (ok && sum == n && !ks.empty()) return ks;
+        ks.clear();
+    }
     const int last = std::min(2, n);
     int rest = n - last;
     while (rest > 0) {
@@ -973,8 +987,8 @@ static int djt_steps(std::vector<Step>& steps, int N, uint32_t mask, int chunked
             d.E_in = (int)djt_extent(N, m0);
             d.E_out = (int)djt_extent(N, m0 + K);
             d.P = d.E_out + H;
-            if (d.P > djt_max_lds_cols())
-                return fail(DRT3D_EUNSUPPORTED, "the DJT is built for N <= 256 (got N = %d)", N);
+            const int ncc = djt_chunks_for(d.P);
+            if (ncc == 0) return fail(DRT3D_EUNSUPPORTED, "the DJT is built for N <= 256 (got N = %d)", N);
             d.T1 = djt_tile_rows(K);
             d.ntiles = (d.E_out + d.T1 - 1) / d.T1;
             d.groups = (1 << (2 * m0)) * (N >> (m0 + K));
@@ -994,7 +1008,7 @@ static int djt_steps(std::vector<Step>& steps, int N, uint32_t mask, int chunked
             snprintf(nm, sizeof nm, "djt_p%d", i + 1);
             Step s; s.kind = S_DJT; s.key = kKeyPass + i; s.name = nm;
             s.waves = 8;
-            s.shape = K;
+            s.shape = K | ncc << 4;
             s.lds = (size_t)NB * (d.T1 + H) * d.P * elem;
             const double in_e = i == 0 ? (double)N * N * N : (double)djt_stage_elems(N, m0);
             const double out_e = (double)djt_stage_elems(N, m0 + K);
