@@ -373,6 +373,11 @@ static int prof_flush()
 // ------------------------------------------------------------------ programs
 enum StepKind { S_DRT = 0, S_DJT = 1, S_TRANSPOSE = 2 };
 
+// Step keys: a step's position in its volume's sequence, the same for every
+// volume of a batched call (forward transposes, passes, adjoint rounds,
+// adjoint combines).
+static const int kKeyTransY = 0, kKeyTransX = 1, kKeyPass = 10, kKeyRound = 40, kKeyCombine = 60;
+
 struct Step {
     int kind = S_DRT;
     int key = 0;  // canonical position (batched merge key)
@@ -416,10 +421,12 @@ struct Program {
 };
 
 // Append the steps as launches, in order (single calls) or merged by key
-// (batched calls: all steps with the same key form one launch). Volumes
-// marked `solo` are never merged: their steps follow the merged launches in
-// per-volume order, so each volume's freshly written buffers are read while
-// they may still sit in the memory-side cache.
+// (batched calls: all steps with the same key form one launch). The passes of
+// volumes marked `solo` are never merged: they run after the merged passes in
+// per-volume order, so each volume's freshly written stage buffers are read
+// while they may still sit in the memory-side cache. Their volume transposes
+// still merge with everyone's: the forward's (keys below kKeyPass) open the
+// program, the adjoint's (kKeyCombine and up) close it.
 static void build_program(Program& prog, const std::vector<std::vector<Step>>& per_volume, bool merge,
                           const std::vector<char>* solo = nullptr)
 {
@@ -430,15 +437,23 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
             for (auto& s : v) { order.push_back(&s); mergeable.push_back(0); }
     } else {
         std::map<int, std::vector<const Step*>> bykey;
-        for (size_t i = 0; i < per_volume.size(); ++i)
-            if (!solo || !(*solo)[i])
-                for (auto& s : per_volume[i]) bykey[s.key].push_back(&s);
-        for (auto& kv : bykey)
-            for (auto* s : kv.second) { order.push_back(s); mergeable.push_back(1); }
+        for (size_t i = 0; i < per_volume.size(); ++i) {
+            const bool so = solo && (*solo)[i];
+            for (auto& s : per_volume[i])
+                if (!so || s.kind == S_TRANSPOSE) bykey[s.key].push_back(&s);
+        }
+        auto take = [&](bool post) {
+            for (auto& kv : bykey)
+                if ((kv.first >= kKeyCombine) == post)
+                    for (auto* s : kv.second) { order.push_back(s); mergeable.push_back(1); }
+        };
+        take(false);
         if (solo)
             for (size_t i = 0; i < per_volume.size(); ++i)
                 if ((*solo)[i])
-                    for (auto& s : per_volume[i]) { order.push_back(&s); mergeable.push_back(0); }
+                    for (auto& s : per_volume[i])
+                        if (s.kind != S_TRANSPOSE) { order.push_back(&s); mergeable.push_back(0); }
+        take(true);
     }
     size_t i = 0;
     while (i < order.size()) {
@@ -710,7 +725,6 @@ static bool choose_tiles(const PassGeom& g, int adjoint, int lds_elems, int& T, 
     return lds_elems_of(ns, L, pad) <= lds_elems;
 }
 
-static const int kKeyTransY = 0, kKeyTransX = 1, kKeyPass = 10, kKeyRound = 40, kKeyCombine = 60;
 
 struct DrtIO {
     const void* in;   // forward: volume; adjoint: projection
@@ -1267,10 +1281,12 @@ static int batched(int kind, int adjoint, int count, const void* const* ins, voi
     char* w = (char*)ws + align256(dsz);
     std::vector<std::vector<Step>> vols(count);
     std::vector<char> solo(count, 0);
+    const char* se = getenv("DRT3D_SOLO_N");  // tuning override of kSoloN
+    const int solo_n = se ? atoi(se) : kSoloN;
     for (int i = 0; i < count; ++i) {
         // a volume this large fills the GPU in every launch on its own:
         // merging it with others only stretches each launch's working set
-        solo[i] = Ns[i] >= kSoloN;
+        solo[i] = Ns[i] >= solo_n;
         DrtIO io{ins[i], outs[i], w};
         if (kind == S_DJT) {
             TRY(djt_steps(vols[i], Ns[i], mask, 0, io));
