@@ -363,7 +363,7 @@ __device__ __forceinline__ void store_tile(const DrtDesc* __restrict__ d, const 
     const int nslot = 1 << (g.Kx + g.Ky);
     const int q0 = g.adjoint ? 0 : g.H;
     const int Eout = d->dst_mode == 0 ? d->E_out : g.N;
-    T* dstbase = d->dst_mode == 0 ? reinterpret_cast<T*>(d->dst) + d->phys[slot] * d->dst_slot_stride
+    T* dstbase = d->dst_mode == 0 ? reinterpret_cast<T*>(d->dst) + d->dphys[slot] * d->dst_slot_stride
                                   : reinterpret_cast<T*>(d->vdst[d->fm[slot].group]);
     const int accum = d->dst_mode == 1 && d->accum[slot];
     const FrameMap f = d->fm[slot];
@@ -411,7 +411,7 @@ __device__ __forceinline__ void store_tile_aligned(const DrtDesc* __restrict__ d
 {
     const int q0 = g.adjoint ? 0 : g.H;
     const int Eout = d->dst_mode == 0 ? d->E_out : g.N;
-    T* dstbase = d->dst_mode == 0 ? reinterpret_cast<T*>(d->dst) + d->phys[slot] * d->dst_slot_stride
+    T* dstbase = d->dst_mode == 0 ? reinterpret_cast<T*>(d->dst) + d->dphys[slot] * d->dst_slot_stride
                                   : reinterpret_cast<T*>(d->vdst[d->fm[slot].group]);
     const int accum = d->dst_mode == 1 && d->accum[slot];
     const FrameMap f = d->fm[slot];
@@ -611,8 +611,26 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
         const int local = (int)(wg - d->wg_begin);
         const int n = d->n, N = d->N, mx0 = d->mx0, my0 = d->my0;
         const int lg_groups = (n - KX) + (n - KY);
-        const int gidx = local & ((1 << lg_groups) - 1);
-        const int slot = local >> lg_groups;
+        int gidx = local & ((1 << lg_groups) - 1);
+        int slot = local >> lg_groups;
+        if (KX == KY && d->xcd_run > 0) {
+            // runs of xcd_run slots; inside a run, work group w takes block
+            // (w / (8 run)) * 8 + w % 8 of slot (w / 8) % run, in the layout's
+            // own block coordinates, then maps it into the slot's frame
+            const int rl = d->xcd_run, ng = 1 << lg_groups;
+            const int run = local / (rl * ng), rem = local - run * rl * ng;
+            const int hi = rem / (8 * rl), lo = rem - hi * 8 * rl;
+            slot = run * rl + lo / 8;
+            const int b = hi * 8 + (lo & 7);
+            const int G = N >> KX;
+            const int b1 = b / G, b2 = b - b1 * G;
+            const FrameMap f = d->fm[slot];
+            // x' runs along the layout's first index (stride N^2) or its second
+            const bool along_first = f.sx == N * N || f.sx == -N * N;
+            const int bx = along_first ? (f.sx > 0 ? b1 : G - 1 - b1) : (f.sx > 0 ? b2 : G - 1 - b2);
+            const int by = along_first ? (f.sy > 0 ? b2 : G - 1 - b2) : (f.sy > 0 ? b1 : G - 1 - b1);
+            gidx = (bx << (n - KY)) | by;
+        }
         const int T_ = d->T, H = d->H, Lp = d->Lp, pad = Lp - L, adjoint = d->adjoint;
         const int gy = gidx & ((1 << (n - KY)) - 1), gx = gidx >> (n - KY);
         const int sx0 = gx & ((1 << mx0) - 1);
@@ -652,7 +670,7 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
             sE = N;
         }
         if (d->dst_mode == 0) {
-            T* base = reinterpret_cast<T*>(d->dst) + d->phys[slot] * d->dst_slot_stride;
+            T* base = reinterpret_cast<T*>(d->dst) + d->dphys[slot] * d->dst_slot_stride;
             rs_dst = make_rsrc(base, (int)d->dst_slot_stride);
             const int c1 = adjoint ? c1b : c1s, c2 = adjoint ? c2b : c2s;
             do_ = ((c1 << n) + c2) * d->P_out;

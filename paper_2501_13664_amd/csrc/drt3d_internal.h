@@ -39,7 +39,13 @@ struct DrtDesc {
     int E_in, P_in, E_out, P_out;
     int T, H, L, Lp;       // tile width, local halo, LDS column length and pitch
     int src_mode, dst_mode, adjoint, nt_store;
-    int phys[kMaxSlots];   // slot -> slot index inside the src/dst stage buffers
+    // > 0: the slots form runs of xcd_run dodecants that read the same volume
+    // layout; work items are ordered so that the run's dodecants take the
+    // same original column block in work groups 8 apart (same XCD, close in
+    // time), sharing its loads through that XCD's L2
+    int xcd_run;
+    int phys[kMaxSlots];   // slot -> slot index inside the source (stage buffer or projections)
+    int dphys[kMaxSlots];  // slot -> slot index inside the destination (dst_mode 0)
     int accum[kMaxSlots];  // dst_mode 1: add into the volume (1) or overwrite (0)
     FrameMap fm[kMaxSlots];
 };

@@ -756,14 +756,41 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
     const int n = ilog2_exact(N);
     const int elem = 4;
     const int nd = popcount12(mask);
-    int dods[12], nd2 = 0;
-    for (int k = 0; k < 12; ++k)
-        if ((mask >> k) & 1) dods[nd2++] = k;
+    // dodecants grouped by the volume layout they read (z-, y-, x-normal),
+    // increasing k inside a group; mrank[k] is k's place in the caller's
+    // projections (increasing k over the mask)
+    int dods[12], nd2 = 0, mrank[12] = {0}, gcount[3] = {0, 0, 0};
+    for (int k = 0, r = 0; k < 12; ++k)
+        if ((mask >> k) & 1) mrank[k] = r++;
+    for (int g = 0; g < 3; ++g)
+        for (int k = 0; k < 12; ++k)
+            if (((mask >> k) & 1) && drt_group(k) == g) { dods[nd2++] = k; ++gcount[g]; }
+    if (adjoint) {
+        // the adjoint's last pass adds the dodecants of one group into one
+        // volume in rounds, one dodecant of each group per round: mixing the
+        // groups inside a chunk makes fewer, fuller rounds
+        int by[3][4], c[3] = {0, 0, 0}, q = 0;
+        for (int i = 0; i < nd; ++i) { const int g = drt_group(dods[i]); by[g][c[g]++] = dods[i]; }
+        for (int r = 0; r < 4; ++r)
+            for (int g = 0; g < 3; ++g)
+                if (r < c[g]) dods[q++] = by[g][r];
+    }
     bool has[3] = {false, false, false};
     for (int i = 0; i < nd; ++i) has[drt_group(dods[i])] = true;
     const size_t vol_bytes = (size_t)N * N * N * elem;
-    const long long per = drt_stage_elems_per_dod(N);
-    const int chunk = chunked ? chunk_size(2 * per * elem, nd) : nd;
+    const long long per = drt_stage_elems_per_dod(N);  // the workspace's bound per dodecant
+    const int chunk_ws = chunked ? chunk_size(2 * per * elem, nd) : nd;
+    const std::vector<PassGeom> P = drt_passes(N, t);
+    const int np = (int)P.size();
+    // stage elements per dodecant of this tuning (pitches rounded to 32)
+    long long per_t = 1;
+    for (int i = 0; i + 1 < np; ++i) per_t = std::max(per_t, (long long)N * N * round32(P[i].E_out));
+    int chunk = (int)std::min<long long>(nd, chunk_ws * per / per_t);
+    // whole layout groups per chunk when every group present has all four
+    // dodecants: the first pass then shares each group's loads (xcd_run)
+    const bool runs4 = (gcount[0] == 0 || gcount[0] == 4) && (gcount[1] == 0 || gcount[1] == 4) &&
+                       (gcount[2] == 0 || gcount[2] == 4);
+    if (runs4 && chunk >= 4 && !adjoint) chunk -= chunk % 4;
 
     char* w = io.ws;
     void* V[3] = {nullptr, nullptr, nullptr};
@@ -771,7 +798,7 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
     if (has[1]) { V[1] = w; w += align256(vol_bytes); }
     if (has[2]) { V[2] = w; w += align256(vol_bytes); }
     void* S[2];
-    S[0] = w; w += align256((size_t)chunk * per * elem);
+    S[0] = w; w += align256((size_t)chunk_ws * per * elem);
     S[1] = w;
 
     const long long out_pitch = 3LL * N - 2;
@@ -793,8 +820,6 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
         }
     }
 
-    const std::vector<PassGeom> P = drt_passes(N, t);
-    const int np = (int)P.size();
     bool seen_group[3] = {false, false, false};
     for (int c0 = 0; c0 < nd; c0 += chunk) {
         const int ns = std::min(chunk, nd - c0);
@@ -813,25 +838,28 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             d.nslots = ns;
             d.E_in = adjoint ? g.E_out : g.E_in;
             d.E_out = adjoint ? g.E_in : g.E_out;
-            for (int s = 0; s < ns; ++s) {
-                d.phys[s] = s;
-                d.fm[s] = drt_frame_map(dods[c0 + s], N);
-            }
             const bool first = step == 0, last = step == np - 1;
+            for (int s = 0; s < ns; ++s) {
+                const int k = dods[c0 + s];
+                d.fm[s] = drt_frame_map(k, N);
+                d.phys[s] = first && adjoint ? mrank[k] : s;   // projections or stage slots
+                d.dphys[s] = last && !adjoint ? mrank[k] : s;  // projections or stage slots
+            }
             if (first && !adjoint) {
                 d.src_mode = 1;
                 for (int i = 0; i < 3; ++i) d.vsrc[i] = V[i];
+                if (runs4 && ns % 4 == 0 && g.Kx == g.Ky && ((N >> g.Kx) * (N >> g.Ky)) % 8 == 0) d.xcd_run = 4;
             } else if (first) {
-                d.src = (const char*)io.in + (size_t)c0 * slot_out * elem;
+                d.src = io.in;
                 d.src_slot_stride = slot_out;
                 d.P_in = (int)out_pitch;
             } else {
                 d.src = S[(step - 1) & 1];
-                d.src_slot_stride = per;
+                d.src_slot_stride = per_t;
                 d.P_in = (int)round32(d.E_in);
             }
             if (last && !adjoint) {
-                d.dst = (char*)io.out + (size_t)c0 * slot_out * elem;
+                d.dst = io.out;
                 d.dst_slot_stride = slot_out;
                 d.P_out = (int)out_pitch;
                 d.nt_store = 1;  // the caller's output is not read back here
@@ -840,7 +868,7 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
                 for (int i = 0; i < 3; ++i) d.vdst[i] = V[i];
             } else {
                 d.dst = S[step & 1];
-                d.dst_slot_stride = per;
+                d.dst_slot_stride = per_t;
                 d.P_out = (int)round32(d.E_out);
             }
             const int K = g.Kx + g.Ky;
@@ -870,7 +898,8 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
                     for (int s = 0; s < ns; ++s) {
                         if (rank[s] != r) continue;
                         const int grp = d.fm[s].group;
-                        e.phys[k] = s;
+                        e.phys[k] = d.phys[s];
+                        e.dphys[k] = d.dphys[s];
                         e.fm[k] = d.fm[s];
                         e.accum[k] = seen_group[grp] ? 1 : 0;
                         seen_group[grp] = true;
