@@ -1,0 +1,43 @@
+// Shape-specialised DRT pass kernels of one (KX, KY) pass shape, compiled
+// once per shape with -DDRT3D_KX=.. -DDRT3D_KY=.. so the shapes build in
+// parallel.
+
+#include "drt3d_kernels.h"
+
+#if !defined(DRT3D_KX) || !defined(DRT3D_KY)
+#error "compile with -DDRT3D_KX=<2|3> -DDRT3D_KY=<2|3>"
+#endif
+
+#define DRT3D_CAT2(a, b, c) a##b##_##c
+#define DRT3D_CAT(a, b, c) DRT3D_CAT2(a, b, c)
+
+namespace drt3d {
+
+template <typename T, int MODE>
+static const void* mode_kernel(int nch)
+{
+#define DRT3D_NC(NC) \
+    if (nch == NC) return reinterpret_cast<const void*>(&fast::drt_pass_fast<T, DRT3D_KX, DRT3D_KY, NC, MODE>);
+    DRT3D_NC(1) DRT3D_NC(2) DRT3D_NC(3) DRT3D_NC(4) DRT3D_NC(5) DRT3D_NC(6)
+#undef DRT3D_NC
+    return nullptr;
+}
+
+template <typename T>
+static const void* shape_kernel(int nch, int mode)
+{
+    switch (mode) {
+    case 0: return mode_kernel<T, 0>(nch);
+    case 1: return mode_kernel<T, 1>(nch);
+    case 2: return mode_kernel<T, 2>(nch);
+    default: return nullptr;
+    }
+}
+
+// mode: 0 forward into a stage buffer, 1 the forward's last pass, 2 adjoint
+const void* DRT3D_CAT(drt_fast_kernel_, DRT3D_KX, DRT3D_KY)(int is_float, int nch, int mode)
+{
+    return is_float ? shape_kernel<float>(nch, mode) : shape_kernel<uint32_t>(nch, mode);
+}
+
+}  // namespace drt3d

@@ -89,15 +89,23 @@ hipError_t launch_drt_pass(int is_float, const DrtDesc* d_descs, int ndesc, long
 // of the kernel that takes LDS rows of `cols` columns (0: none does).
 int djt_tile_rows(int K);
 int djt_chunks_for(int cols);
-hipError_t launch_djt_pass(int is_float, int K, int ncc, const DjtDesc* d_descs, int ndesc, long long total_wg,
-                           int grid, size_t lds_bytes, hipStream_t s);
+hipError_t launch_djt_pass(int is_float, int K, int ncc, int nco, const DjtDesc* d_descs, int ndesc,
+                           long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_transpose(int is_float, const TransDesc* d_descs, int ndesc, long long total_wg,
                             hipStream_t s);
 hipError_t set_drt_lds_limit(int is_float, size_t bytes);
+// Kernel handles of the shape-specialised DRT passes (one translation unit
+// per shape) and of the DJT passes.
+const void* drt_fast_kernel_3_3(int is_float, int nch, int mode);
+const void* drt_fast_kernel_2_2(int is_float, int nch, int mode);
+const void* drt_fast_kernel_3_2(int is_float, int nch, int mode);
+const void* drt_fast_kernel_2_3(int is_float, int nch, int mode);
+const void* djt_pass_kernel_ptr(int is_float, int K, int ncc, int nco);
 // Shape-specialised DRT pass kernels (eight wavefronts per work group).
-// final_pass: every descriptor is the forward's last pass (caller's output).
+// mode: 0 forward into a stage buffer, 1 the forward's last pass (every
+// descriptor writes the caller's output), 2 adjoint.
 int drt_fast_available(int kx, int ky, int nch);
-hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int final_pass, const DrtDesc* d_descs,
-                           int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
+hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int mode, const DrtDesc* d_descs, int ndesc,
+                           long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
 
 }  // namespace drt3d

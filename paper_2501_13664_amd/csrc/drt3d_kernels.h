@@ -1,0 +1,1025 @@
+// Device code of the drt3d library for gfx950 (CDNA4, wave64).
+//
+// DRT passes (forward eq. (11), adjoint eq. (17)). The stage map of eq. (11)
+// shifts along the displacement axis only, and its x-part (slope s1, block
+// bit v1) and y-part (s2, v2) add independent shifts, so the x- and y-stages
+// of a dodecant commute and can be grouped freely (the 2D transform applied
+// twice, Sec. 6.3). A pass runs the x-stages mx0..mx0+Kx-1 and the y-stages
+// my0..my0+Ky-1 on a group of 2^Kx x 2^Ky columns that exchange data only
+// among themselves (those sharing the low slope bits sx0, sy0 and the block
+// bits above each range). The group's columns, over one displacement tile plus
+// a halo, sit in LDS; every stage is an in-place butterfly over a column pair,
+// one wavefront per pair, lanes along the displacement: every LDS access of a
+// wave is 64 consecutive words and every shift is wave-uniform.
+//
+// Slot order: LDS slot p = px + (py << Kx). Before an x-stage j, bits [0, j)
+// of px hold the slope bits already produced (newest in bit j-1) and bits
+// [j, Kx) the remaining block index; the pair (p, p + 2^j) are the two block
+// halves of one slope and their two results (new slope bit 0, 1) overwrite the
+// same two slots. After the pass slot p holds slope (bitrev(px), bitrev(py)).
+//
+// Skewed origins. At x-stage j the shift of a pair is its slope
+// t + sx0 * 2^j plus the new bit; sx0 is common to the group. Column w of the
+// group is loaded with its displacement origin lowered by sx0*w + sy0*w_y, so
+// the common part of every shift is absorbed by the origins (the pair's
+// origins differ by exactly sx0 * 2^j) and LDS only sees the local shift
+// t + bit <= 2^j; after the last stage all slots share one origin. The halo of
+// a tile is therefore (2^Kx - 1) + (2^Ky - 1) whatever stages the pass covers.
+// The adjoint runs the same butterflies transposed and in reverse order; its
+// outputs inherit the skew instead of its inputs.
+//
+// DJT passes (eq. (15)): K stages fused per launch; see djt_pass_kernel.
+//
+// This header holds the kernels as templates. The translation units that
+// instantiate them (drt3d_device.hip, drt3d_fast.hip once per pass shape,
+// drt3d_djt.hip) compile in parallel.
+
+#pragma once
+
+#include "drt3d_internal.h"
+
+namespace drt3d {
+
+__device__ __forceinline__ int bitrev(int x, int bits)
+{
+    return bits ? (int)(__brev((unsigned)x) >> (32 - bits)) : 0;
+}
+
+template <typename T>
+__device__ __forceinline__ T zero_of() { return T(0); }
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Vec4;
+template <> struct Vec4<uint32_t> { using type = u32x4; };
+template <> struct Vec4<float> { using type = f32x4; };
+
+__device__ __forceinline__ int find_desc_drt(const DrtDesc* __restrict__ descs, int ndesc, long long wg)
+{
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].wg_begin <= wg) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// LDS layout of a work item: [pad zeros][slot 0: L][pad zeros][slot 1: L] ...
+// [slot n-1: L][pad zeros], L a multiple of 64, slot pitch Lp = L + pad. Reads
+// that leave a slot by up to `pad` positions (below in the forward, above in
+// the adjoint) hit zeros, so the stage loops carry no bounds checks; the pad
+// covers the largest shift of the pass.
+__device__ __forceinline__ int slot_offset(int p, int Lp, int pad) { return pad + p * Lp; }
+
+// Raw buffer access with the hardware range check: a buffer resource covers
+// one column (or one volume line) exactly, so reads outside it return 0 and
+// writes outside it are dropped, with no compare in the code. Offsets are in
+// bytes; a negative offset wraps to a huge one and is out of range too.
+constexpr int kBufferConfig = 0x00020000;  // gfx9 raw-buffer dword 3
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const T* base, int elems)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, elems * (int)sizeof(T), kBufferConfig);
+}
+
+__device__ __forceinline__ uint32_t bload(__amdgpu_buffer_rsrc_t r, int off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, uint32_t v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
+}
+
+template <typename T> __device__ __forceinline__ uint32_t to_bits(T v) { return __builtin_bit_cast(uint32_t, v); }
+template <typename T> __device__ __forceinline__ T from_bits(uint32_t v) { return __builtin_bit_cast(T, v); }
+
+// Forward radix-2 step (one stage of one axis) on the pair (s0, s1) with
+// local shift t: s0[l] += s1[l-t], s1[l] = s0_old[l] + s1[l-t-1]. In place,
+// 64-position chunks from the top down: a chunk reads only at or below its
+// own positions, and writes after all of its reads.
+template <typename T, int NCH>
+__device__ __forceinline__ void step2_fwd(T* s0, T* s1, int nch, int t, int lane)
+{
+    T* w0 = s0 + lane;
+    T* w1 = s1 + lane;
+    const T* r1 = s1 + lane - t - 1;
+    const int n = NCH ? NCH : nch;
+#pragma unroll
+    for (int c = n - 1; c >= 0; --c) {
+        const T a = w0[64 * c], b1 = r1[64 * c], b0 = r1[64 * c + 1];
+        w0[64 * c] = a + b0;
+        w1[64 * c] = a + b1;
+    }
+}
+
+// Forward radix-4 step: x-stage and y-stage of the same index fused, which is
+// the four-term stage map of eq. (11) itself. Slot s_ab receives the slope
+// whose new x bit is a and new y bit is b.
+template <typename T, int NCH>
+__device__ __forceinline__ void step4_fwd(T* s00, T* s10, T* s01, T* s11, int nch, int tx, int ty, int lane)
+{
+    T* w00 = s00 + lane;
+    T* w10 = s10 + lane;
+    T* w01 = s01 + lane;
+    T* w11 = s11 + lane;
+    const T* r10 = s10 + lane - tx - 1;
+    const T* r01 = s01 + lane - ty - 1;
+    const T* r11 = s11 + lane - tx - ty - 2;
+    const int n = NCH ? NCH : nch;
+#pragma unroll
+    for (int c = n - 1; c >= 0; --c) {
+        const int o = 64 * c;
+        const T f00 = w00[o];
+        const T f10b = r10[o], f10a = r10[o + 1];
+        const T f01b = r01[o], f01a = r01[o + 1];
+        const T f11c = r11[o], f11b = r11[o + 1], f11a = r11[o + 2];
+        const T x0 = f00 + f10a, x1 = f00 + f10b;
+        w00[o] = x0 + (f01a + f11a);
+        w10[o] = x1 + (f01a + f11b);
+        w01[o] = x0 + (f01b + f11b);
+        w11[o] = x1 + (f01b + f11c);
+    }
+}
+
+// Adjoint radix-2 step (transpose of step2_fwd), chunks from the bottom up.
+template <typename T, int NCH>
+__device__ __forceinline__ void step2_adj(T* s0, T* s1, int nch, int t, int lane)
+{
+    T* w0 = s0 + lane;
+    T* w1 = s1 + lane;
+    const T* r0 = s0 + lane + t;
+    const T* r1 = s1 + lane + t + 1;
+    const int n = NCH ? NCH : nch;
+#pragma unroll
+    for (int c = 0; c < n; ++c) {
+        const int o = 64 * c;
+        const T a0 = w0[o], a1 = w1[o], c0 = r0[o], c1 = r1[o];
+        w0[o] = a0 + a1;
+        w1[o] = c0 + c1;
+    }
+}
+
+// Adjoint radix-4 step (transpose of step4_fwd).
+template <typename T, int NCH>
+__device__ __forceinline__ void step4_adj(T* s00, T* s10, T* s01, T* s11, int nch, int tx, int ty, int lane)
+{
+    T* w00 = s00 + lane;
+    T* w10 = s10 + lane;
+    T* w01 = s01 + lane;
+    T* w11 = s11 + lane;
+    const int txy = tx + ty;
+    const int n = NCH ? NCH : nch;
+#pragma unroll
+    for (int c = 0; c < n; ++c) {
+        const int o = 64 * c;
+        const T c00 = (w00[o] + w10[o]) + (w01[o] + w11[o]);
+        const T c10 = (w00[o + tx] + w10[o + tx + 1]) + (w01[o + tx] + w11[o + tx + 1]);
+        const T c01 = (w00[o + ty] + w10[o + ty]) + (w01[o + ty + 1] + w11[o + ty + 1]);
+        const T c11 = (w00[o + txy] + w10[o + txy + 1]) + (w01[o + txy + 1] + w11[o + txy + 2]);
+        w00[o] = c00;
+        w10[o] = c10;
+        w01[o] = c01;
+        w11[o] = c11;
+    }
+}
+
+// All stages of one pass on the LDS slots (forward or adjoint). x-stage j and
+// y-stage j run together as one radix-4 step while both axes have them; the
+// rest run as radix-2 steps. Each axis keeps its stage order, which is all the
+// in-place slot convention needs.
+template <typename T, int NCH>
+__device__ __forceinline__ void run_stages(T* lds, int Lp, int pad, int nch, int Kx, int Ky, int adjoint, int wave,
+                                           int nwaves, int lane)
+{
+    const int nslot = 1 << (Kx + Ky);
+    const int xmask = (1 << Kx) - 1;
+    const int kmax = Kx > Ky ? Kx : Ky;
+    for (int jj = 0; jj < kmax; ++jj) {
+        const int j = adjoint ? kmax - 1 - jj : jj;
+        const bool hx = j < Kx, hy = j < Ky;
+        const int bx = 1 << j, by = 1 << (Kx + j);
+        if (hx && hy) {
+            const int nq = nslot >> 2;
+            for (int q = wave; q < nq; q += nwaves) {
+                // insert zero bits at positions j (x) and Kx + j (y)
+                int p = ((q >> j) << (j + 1)) | (q & (bx - 1));
+                p = ((p >> (Kx + j)) << (Kx + j + 1)) | (p & (by - 1));
+                const int tx = bitrev(p & (bx - 1), j);
+                const int ty = bitrev((p >> Kx) & (bx - 1), j);
+                T* s00 = lds + slot_offset(p, Lp, pad);
+                if (!adjoint) step4_fwd<T, NCH>(s00, s00 + bx * Lp, s00 + by * Lp, s00 + (bx + by) * Lp, nch, tx, ty, lane);
+                else step4_adj<T, NCH>(s00, s00 + bx * Lp, s00 + by * Lp, s00 + (bx + by) * Lp, nch, tx, ty, lane);
+            }
+        } else {
+            const int bit = hx ? j : Kx + j;
+            const int h = 1 << bit;
+            const int np = nslot >> 1;
+            for (int q = wave; q < np; q += nwaves) {
+                const int p = ((q >> bit) << (bit + 1)) | (q & (h - 1));
+                const int axis_bits = hx ? (p & xmask) : (p >> Kx);
+                const int t = bitrev(axis_bits & ((1 << j) - 1), j);
+                T* s0 = lds + slot_offset(p, Lp, pad);
+                if (!adjoint) step2_fwd<T, NCH>(s0, s0 + h * Lp, nch, t, lane);
+                else step2_adj<T, NCH>(s0, s0 + h * Lp, nch, t, lane);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Geometry of one work item (one column group, one displacement tile, one
+// dodecant slot), shared by its load, stage and store phases.
+struct ItemGeom {
+    int N, n, Kx, Ky, mx0, my0;
+    int sx0, sy0, vhx, vhy;
+    int L, Lp, pad, T, H, d0;
+    int adjoint;
+};
+
+// Column of slot p in its stage buffer (or frame view): block (px, py) for
+// the forward input / adjoint output, slope (bitrev px, bitrev py) for the
+// forward output / adjoint input.
+__device__ __forceinline__ void block_col(const ItemGeom& g, int p, int& c1, int& c2)
+{
+    const int px = p & ((1 << g.Kx) - 1), py = p >> g.Kx;
+    c1 = g.sx0 + (px << g.mx0) + g.vhx;
+    c2 = g.sy0 + (py << g.my0) + g.vhy;
+}
+
+__device__ __forceinline__ void slope_col(const ItemGeom& g, int p, int& c1, int& c2)
+{
+    const int px = p & ((1 << g.Kx) - 1), py = p >> g.Kx;
+    c1 = bitrev(px, g.Kx) + (g.sx0 << g.Kx) + g.vhx;
+    c2 = bitrev(py, g.Ky) + (g.sy0 << g.Ky) + g.vhy;
+}
+
+__device__ __forceinline__ int skew_of(const ItemGeom& g, int p)
+{
+    return g.sx0 * (p & ((1 << g.Kx) - 1)) + g.sy0 * (p >> g.Kx);
+}
+
+// Buffer resource and byte offset of lane 0 for a column whose element dd is
+// at col[sd * dd], valid for dd in [0, E), addressed from displacement dd0.
+template <typename T>
+__device__ __forceinline__ void column_rsrc(const T* col, int sd, int E, int dd0, int lane,
+                                            __amdgpu_buffer_rsrc_t& rs, int& voff)
+{
+    if (sd > 0) {
+        rs = make_rsrc(col, E);
+        voff = 4 * (dd0 + lane);
+    } else {  // element dd at col - dd: the resource starts at dd = E - 1
+        rs = make_rsrc(col - (E - 1), E);
+        voff = 4 * (E - 1 - dd0 - lane);
+    }
+}
+
+// Buffer resource and lane-0 byte offset of the column that LDS slot p loads
+// for the tile at g.d0: block (px, py) at a skewed origin (forward) or slope
+// (bitrev px, bitrev py) at the common origin (adjoint).
+template <typename T>
+__device__ __forceinline__ void src_column(const DrtDesc* __restrict__ d, const ItemGeom& g, int slot, int p, int lane,
+                                           __amdgpu_buffer_rsrc_t& rs, int& voff, int& step)
+{
+    int c1, c2, dd0;
+    if (!g.adjoint) {
+        block_col(g, p, c1, c2);
+        dd0 = g.d0 - g.H - skew_of(g, p);
+    } else {
+        slope_col(g, p, c1, c2);
+        dd0 = g.d0;
+    }
+    if (d->src_mode == 0) {
+        const T* base = reinterpret_cast<const T*>(d->src) + d->phys[slot] * d->src_slot_stride;
+        column_rsrc(base + (((long long)c1 << g.n) + c2) * d->P_in, 1, d->E_in, dd0, lane, rs, voff);
+        step = 256;
+    } else {
+        const FrameMap f = d->fm[slot];
+        const T* base = reinterpret_cast<const T*>(d->vsrc[f.group]);
+        column_rsrc(base + ((long long)f.base + (long long)f.sx * c1 + (long long)f.sy * c2), f.sd, g.N, dd0, lane,
+                    rs, voff);
+        step = 256 * f.sd;
+    }
+}
+
+// Issues every global load of the wave's slots (p = wave + i * nwaves) for the
+// tile at g.d0: SPW * NCH loads in flight at once.
+template <typename T, int NCH, int SPW>
+__device__ __forceinline__ void load_regs(const DrtDesc* __restrict__ d, const ItemGeom& g, int slot, int wave,
+                                          int nwaves, int lane, uint32_t (&v)[SPW][NCH])
+{
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) {
+        __amdgpu_buffer_rsrc_t rs;
+        int voff, step;
+        src_column<T>(d, g, slot, wave + i * nwaves, lane, rs, voff, step);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) v[i][c] = bload(rs, voff + step * c);
+    }
+}
+
+template <typename T, int NCH, int SPW>
+__device__ __forceinline__ void regs_to_lds(const ItemGeom& g, T* lds, int wave, int nwaves, int lane,
+                                            const uint32_t (&v)[SPW][NCH])
+{
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) {
+        T* s = lds + slot_offset(wave + i * nwaves, g.Lp, g.pad) + lane;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) s[64 * c] = from_bits<T>(v[i][c]);
+    }
+}
+
+// Unpipelined load for shapes without a register buffer (NCH = 0 or many
+// slots per wave): per slot, all chunks in flight, then written to LDS.
+template <typename T, int NCH>
+__device__ __forceinline__ void load_direct(const DrtDesc* __restrict__ d, const ItemGeom& g, int slot, T* lds,
+                                            int wave, int nwaves, int lane)
+{
+    const int nch = NCH ? NCH : (g.L >> 6);
+    const int nslot = 1 << (g.Kx + g.Ky);
+    for (int p = wave; p < nslot; p += nwaves) {
+        __amdgpu_buffer_rsrc_t rs;
+        int voff, step;
+        src_column<T>(d, g, slot, p, lane, rs, voff, step);
+        T* s = lds + slot_offset(p, g.Lp, g.pad) + lane;
+        if (NCH) {
+            uint32_t v[NCH ? NCH : 1];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) v[c] = bload(rs, voff + step * c);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) s[64 * c] = from_bits<T>(v[c]);
+        } else {
+            for (int c = 0; c < nch; ++c) s[64 * c] = from_bits<T>(bload(rs, voff + step * c));
+        }
+    }
+}
+
+// Stores the tile at g.d0 of every slot. The destination column is one buffer
+// resource: writes outside [0, E) are dropped; positions past the tile width
+// (last chunk) are masked.
+template <typename T>
+__device__ __forceinline__ void store_tile(const DrtDesc* __restrict__ d, const ItemGeom& g, int slot, const T* lds,
+                                           int wave, int nwaves, int lane)
+{
+    const int nslot = 1 << (g.Kx + g.Ky);
+    const int q0 = g.adjoint ? 0 : g.H;
+    const int Eout = d->dst_mode == 0 ? d->E_out : g.N;
+    T* dstbase = d->dst_mode == 0 ? reinterpret_cast<T*>(d->dst) + d->dphys[slot] * d->dst_slot_stride
+                                  : reinterpret_cast<T*>(d->vdst[d->fm[slot].group]);
+    const int accum = d->dst_mode == 1 && d->accum[slot];
+    const FrameMap f = d->fm[slot];
+    const int sdv = d->dst_mode == 0 ? 1 : f.sd;
+    const int step = 256 * sdv;
+    const int last = (g.T - 1) >> 6;  // chunk holding the tile's end
+    const bool last_live = 64 * last + lane < g.T;
+    for (int p = wave; p < nslot; p += nwaves) {
+        int c1, c2, dd0;
+        if (!g.adjoint) {  // common origin: positions H.. hold dd = d0..
+            slope_col(g, p, c1, c2);
+            dd0 = g.d0;
+        } else {           // child column (px, py) at its skewed origin
+            block_col(g, p, c1, c2);
+            dd0 = g.d0 - skew_of(g, p);
+        }
+        T* col = d->dst_mode == 0 ? dstbase + (((long long)c1 << g.n) + c2) * d->P_out
+                                  : dstbase + ((long long)f.base + (long long)f.sx * c1 + (long long)f.sy * c2);
+        __amdgpu_buffer_rsrc_t rs;
+        int voff;
+        column_rsrc(col, sdv, Eout, dd0, lane, rs, voff);
+        const T* s = lds + slot_offset(p, g.Lp, g.pad) + q0 + lane;
+        for (int c = 0; c <= last; ++c) {
+            if (c < last || last_live) {
+                T v = s[64 * c];
+                const int off = voff + step * c;
+                if (accum) v += from_bits<T>(bload(rs, off));
+                bstore(rs, off, to_bits(v));
+            }
+        }
+    }
+}
+
+// Line-aligned store of the tile at g.d0 for the wave's slots. HBM writes are
+// cheapest as whole 128-byte lines, and a column's tile rarely starts or ends
+// on one, so each tile writes only the lines it completes: elements from the
+// last line boundary the previous tile reached (kept in `carry`, at most 31
+// of them) up to the last line boundary inside this tile, or to the column
+// end on the last tile. The tail goes into `carry` for the next tile. Lines
+// split between two columns at a column start stay partial. Needs T >= 32.
+template <typename T, int SPW>
+__device__ __forceinline__ void store_tile_aligned(const DrtDesc* __restrict__ d, const ItemGeom& g, int slot,
+                                                   const T* lds, int wave, int nwaves, int lane, bool last_tile,
+                                                   uint32_t (&carry)[SPW])
+{
+    const int q0 = g.adjoint ? 0 : g.H;
+    const int Eout = d->dst_mode == 0 ? d->E_out : g.N;
+    T* dstbase = d->dst_mode == 0 ? reinterpret_cast<T*>(d->dst) + d->dphys[slot] * d->dst_slot_stride
+                                  : reinterpret_cast<T*>(d->vdst[d->fm[slot].group]);
+    const int accum = d->dst_mode == 1 && d->accum[slot];
+    const FrameMap f = d->fm[slot];
+    const int sdv = d->dst_mode == 0 ? 1 : f.sd;
+#pragma unroll
+    for (int i = 0; i < SPW; ++i) {
+        const int p = wave + i * nwaves;
+        int c1, c2, dd0;
+        if (!g.adjoint) {  // common origin: positions H.. hold dd = d0..
+            slope_col(g, p, c1, c2);
+            dd0 = g.d0;
+        } else {           // child column (px, py) at its skewed origin
+            block_col(g, p, c1, c2);
+            dd0 = g.d0 - skew_of(g, p);
+        }
+        const long long cofs = d->dst_mode == 0 ? (((long long)c1 << g.n) + c2) * d->P_out
+                                                : (long long)f.base + (long long)f.sx * c1 + (long long)f.sy * c2;
+        // element index of displacement dd is cofs + sdv * dd; a line boundary
+        // at dd means that index (for sdv = -1: index + 1) is a multiple of 32.
+        const int mis = sdv > 0 ? (int)(cofs & 31) : (int)((cofs + 1) & 31);
+        auto line_floor = [&](int x) { return sdv > 0 ? x - ((mis + x) & 31) : x - ((x - mis) & 31); };
+        const int fbeg = dd0 <= 0 ? dd0 : line_floor(dd0);   // first dd written now
+        const int fend = last_tile ? dd0 + g.T : line_floor(dd0 + g.T);
+        __amdgpu_buffer_rsrc_t rs;
+        int voff;
+        column_rsrc(dstbase + cofs, sdv, Eout, fbeg, lane, rs, voff);
+        const T* s = lds + slot_offset(p, g.Lp, g.pad) + q0 - dd0;  // s[dd] holds displacement dd
+        const int cnt = fend - fbeg;
+        for (int c = 0; 64 * c < cnt; ++c) {
+            const int k = 64 * c + lane;
+            if (k < cnt) {
+                const int dd = fbeg + k;
+                T v = dd < dd0 ? from_bits<T>(carry[i]) : s[dd];
+                const int off = voff + 256 * sdv * c;
+                if (accum) v += from_bits<T>(bload(rs, off));
+                bstore(rs, off, to_bits(v));
+            }
+        }
+        // tail [fend, dd0 + T) for the next tile: lane k holds dd = fend + k
+        if (!last_tile) {
+            const int tail = dd0 + g.T - fend;
+            carry[i] = lane < tail ? to_bits(s[fend + lane]) : 0u;
+        }
+    }
+}
+
+__device__ __forceinline__ void zero_pads_fn(void* lds_raw, int elem_bytes, const ItemGeom& g, int wave, int nwaves,
+                                             int lane)
+{
+    uint32_t* lds = reinterpret_cast<uint32_t*>(lds_raw);
+    const int nslot = 1 << (g.Kx + g.Ky);
+    for (int p = wave; p <= nslot; p += nwaves)
+        if (lane < g.pad) lds[p * g.Lp + lane] = 0u;
+    (void)elem_bytes;
+}
+
+// All tiles of one work item (one column group of one slot). With a register
+// buffer (SPW > 0) the next tile's loads are issued before the current tile's
+// stages run, so global latency overlaps LDS work.
+template <typename T, int NCH, int SPW>
+__device__ __forceinline__ void process_group(const DrtDesc* __restrict__ d, ItemGeom& g, int slot, int ntiles,
+                                              T* lds, int wave, int nwaves, int lane)
+{
+    const int nch = NCH ? NCH : (g.L >> 6);
+    zero_pads_fn(lds, sizeof(T), g, wave, nwaves, lane);
+    if constexpr (SPW > 0) {
+        uint32_t v[SPW][NCH];
+        uint32_t carry[SPW];
+#pragma unroll
+        for (int i = 0; i < SPW; ++i) carry[i] = 0u;
+        g.d0 = 0;
+        load_regs<T, NCH, SPW>(d, g, slot, wave, nwaves, lane, v);
+        for (int tile = 0; tile < ntiles; ++tile) {
+            g.d0 = tile * g.T;
+            regs_to_lds<T, NCH, SPW>(g, lds, wave, nwaves, lane, v);
+            __syncthreads();
+            if (tile + 1 < ntiles) {
+                ItemGeom gn = g;
+                gn.d0 = (tile + 1) * g.T;
+                load_regs<T, NCH, SPW>(d, gn, slot, wave, nwaves, lane, v);
+            }
+            run_stages<T, NCH>(lds, g.Lp, g.pad, nch, g.Kx, g.Ky, g.adjoint, wave, nwaves, lane);
+            store_tile_aligned<T, SPW>(d, g, slot, lds, wave, nwaves, lane, tile + 1 == ntiles, carry);
+            __syncthreads();
+        }
+    } else {
+        for (int tile = 0; tile < ntiles; ++tile) {
+            g.d0 = tile * g.T;
+            load_direct<T, NCH>(d, g, slot, lds, wave, nwaves, lane);
+            __syncthreads();
+            run_stages<T, NCH>(lds, g.Lp, g.pad, nch, g.Kx, g.Ky, g.adjoint, wave, nwaves, lane);
+            store_tile<T>(d, g, slot, lds, wave, nwaves, lane);
+            __syncthreads();
+        }
+    }
+}
+
+// Register-buffer shape: SPW slots per wave, NCH chunks, at most 48 values.
+template <typename T, int NCH>
+__device__ __forceinline__ void dispatch_spw(const DrtDesc* __restrict__ d, ItemGeom& g, int slot, int ntiles, T* lds,
+                                             int wave, int nwaves, int lane)
+{
+    const int nslot = 1 << (g.Kx + g.Ky);
+    const int spw = (nslot % nwaves == 0) ? nslot / nwaves : 0;
+    if (NCH && spw == 8 && 8 * NCH <= 48) process_group<T, NCH, (NCH && 8 * NCH <= 48) ? 8 : 0>(d, g, slot, ntiles, lds, wave, nwaves, lane);
+    else if (NCH && spw == 4 && 4 * NCH <= 48) process_group<T, NCH, (NCH && 4 * NCH <= 48) ? 4 : 0>(d, g, slot, ntiles, lds, wave, nwaves, lane);
+    else if (NCH && spw == 2 && 2 * NCH <= 48) process_group<T, NCH, (NCH && 2 * NCH <= 48) ? 2 : 0>(d, g, slot, ntiles, lds, wave, nwaves, lane);
+    else if (NCH && spw == 1) process_group<T, NCH, NCH ? 1 : 0>(d, g, slot, ntiles, lds, wave, nwaves, lane);
+    else process_group<T, NCH, 0>(d, g, slot, ntiles, lds, wave, nwaves, lane);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512)
+drt_pass_kernel(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwaves = blockDim.x >> 6;
+
+    // A work item is one column group of one dodecant slot; its work group
+    // walks the group's displacement tiles in order, so the cache lines that a
+    // tile boundary splits are completed in the same L2 and the halo a tile
+    // shares with the previous one is read from it.
+    for (long long wg = blockIdx.x; wg < total_wg; wg += gridDim.x) {
+        const DrtDesc* d = descs + find_desc_drt(descs, ndesc, wg);
+        const int local = (int)(wg - d->wg_begin);
+        const int lg_groups = (d->n - d->Kx) + (d->n - d->Ky);
+        const int gidx = local & ((1 << lg_groups) - 1);
+        const int slot = local >> lg_groups;
+
+        ItemGeom g;
+        g.N = d->N; g.n = d->n;
+        g.Kx = d->Kx; g.Ky = d->Ky; g.mx0 = d->mx0; g.my0 = d->my0;
+        g.L = d->L; g.Lp = d->Lp; g.pad = g.Lp - g.L; g.T = d->T; g.H = d->H;
+        g.adjoint = d->adjoint;
+        g.d0 = 0;
+        const int gy = gidx & (d->groups_y - 1), gx = gidx >> (g.n - g.Ky);
+        g.sx0 = gx & ((1 << g.mx0) - 1);
+        g.vhx = (gx >> g.mx0) << (g.mx0 + g.Kx);
+        g.sy0 = gy & ((1 << g.my0) - 1);
+        g.vhy = (gy >> g.my0) << (g.my0 + g.Ky);
+        // adjoint outputs are skewed by up to smax: the group needs fewer tiles
+        const int span = g.adjoint ? d->E_out + g.sx0 * ((1 << g.Kx) - 1) + g.sy0 * ((1 << g.Ky) - 1) : d->E_out;
+        const int ntiles = min(d->ntiles, (span + g.T - 1) / g.T);
+
+        switch (g.L >> 6) {
+            case 1: dispatch_spw<T, 1>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+            case 2: dispatch_spw<T, 2>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+            case 3: dispatch_spw<T, 3>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+            case 4: dispatch_spw<T, 4>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+            case 5: dispatch_spw<T, 5>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+            case 6: dispatch_spw<T, 6>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+            default: dispatch_spw<T, 0>(d, g, slot, ntiles, lds, wave, nwaves, lane); break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Shape-specialised pass kernel: KX x-stages, KY y-stages (KX, KY <= 3,
+// 2^(KX+KY) >= 8 columns), L = 64 * NCH, eight wavefronts. Wave w owns the
+// slots p = w + 8 i, which share the x index px = w mod 2^KX, so a slot's
+// column offset is a per-wave base plus a per-slot stride. Each side of the
+// pass (source, destination) is one buffer resource over its whole region (a
+// stage buffer slot, one dodecant of the output, or the volume; regions below
+// 2^31 bytes); column offsets travel in VGPRs, so the hardware range check
+// covers the full offset, and each column's own range [0, E) is enforced in
+// the lanes: out-of-range loads are replaced by zero, out-of-range stores are
+// masked.
+namespace fast {
+
+constexpr int NW = 8;
+
+template <int KX>
+__device__ __forceinline__ int py_of(int wave, int i) { return (wave >> KX) + i * (NW >> KX); }
+
+// FINAL: the forward's last pass, whose output columns are the caller's
+// projections. A column (s1, s2) is zero past dd = N-1+s1+s2 (the support of
+// eq. (9)), so a tile past the support of every column of the group is written
+// as zeros straight from registers, with no loads and no LDS stages.
+// MODE: 0 a forward pass into a stage buffer, 1 the forward's last pass
+// (FINAL), 2 an adjoint pass; fixing it at compile time drops the other
+// modes' bookkeeping from the kernel.
+template <typename T, int KX, int KY, int NCH, int MODE>
+__global__ void __launch_bounds__(512)
+drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
+{
+    constexpr bool FINAL = MODE == 1;
+    constexpr int adjoint = MODE == 2 ? 1 : 0;
+    constexpr int NS = 1 << (KX + KY), SPW = NS / NW, L = 64 * NCH;
+    static_assert(NS >= 8 && KX <= 3 && KY <= 3, "shape");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int px = wave & ((1 << KX) - 1);
+    const int rpx = bitrev(px, KX);
+
+    for (long long wg = blockIdx.x; wg < total_wg; wg += gridDim.x) {
+        const DrtDesc* d = descs + find_desc_drt(descs, ndesc, wg);
+        const int local = (int)(wg - d->wg_begin);
+        const int n = d->n, N = d->N, mx0 = d->mx0, my0 = d->my0;
+        const int lg_groups = (n - KX) + (n - KY);
+        int gidx = local & ((1 << lg_groups) - 1);
+        int slot = local >> lg_groups;
+        if (KX == KY && d->xcd_run > 0) {
+            // runs of xcd_run slots; inside a run, work group w takes block
+            // (w / (8 run)) * 8 + w % 8 of slot (w / 8) % run, in the layout's
+            // own block coordinates, then maps it into the slot's frame
+            const int rl = d->xcd_run, ng = 1 << lg_groups;
+            const int run = local / (rl * ng), rem = local - run * rl * ng;
+            const int hi = rem / (8 * rl), lo = rem - hi * 8 * rl;
+            slot = run * rl + lo / 8;
+            const int b = hi * 8 + (lo & 7);
+            const int G = N >> KX;
+            const int b1 = b / G, b2 = b - b1 * G;
+            const FrameMap f = d->fm[slot];
+            // x' runs along the layout's first index (stride N^2) or its second
+            const bool along_first = f.sx == N * N || f.sx == -N * N;
+            const int bx = along_first ? (f.sx > 0 ? b1 : G - 1 - b1) : (f.sx > 0 ? b2 : G - 1 - b2);
+            const int by = along_first ? (f.sy > 0 ? b2 : G - 1 - b2) : (f.sy > 0 ? b1 : G - 1 - b1);
+            gidx = (bx << (n - KY)) | by;
+        }
+        const int T_ = d->T, H = d->H, Lp = d->Lp, pad = Lp - L;
+        const int gy = gidx & ((1 << (n - KY)) - 1), gx = gidx >> (n - KY);
+        const int sx0 = gx & ((1 << mx0) - 1);
+        const int vhx = (gx >> mx0) << (mx0 + KX);
+        const int sy0 = gy & ((1 << my0) - 1);
+        const int vhy = (gy >> my0) << (my0 + KY);
+        const int span = adjoint ? d->E_out + sx0 * ((1 << KX) - 1) + sy0 * ((1 << KY) - 1) : d->E_out;
+        const int ntiles = min(d->ntiles, (span + T_ - 1) / T_);
+        // tiles [0, nlive) hold the group's support, the rest are zero (FINAL)
+        int nlive = ntiles;
+        if (FINAL) {
+            const int supp = N - 1 + (sx0 << KX) + (1 << KX) - 1 + (sy0 << KY) + (1 << KY) - 1;
+            nlive = min(ntiles, supp / T_ + 1);
+        }
+        const FrameMap fm = d->fm[slot];
+
+        // block column (px, py): c1 = sx0 + (px << mx0) + vhx, c2 = sy0 + (py << my0) + vhy
+        // slope column:          c1 = bitrev(px) + (sx0 << KX) + vhx, c2 = bitrev(py) + (sy0 << KY) + vhy
+        const int c1b = sx0 + (px << mx0) + vhx, c2b = sy0 + vhy;
+        const int c1s = rpx + (sx0 << KX) + vhx, c2s = (sy0 << KY) + vhy;
+        // source: element of slot i at displacement dd is region[o + y(i)*ys + sd*dd]
+        __amdgpu_buffer_rsrc_t rs_src, rs_dst;
+        int so, sys, ssd, sE, do_, dys, dsd, dE;
+        if (d->src_mode == 0) {
+            const T* base = reinterpret_cast<const T*>(d->src) + d->phys[slot] * d->src_slot_stride;
+            rs_src = make_rsrc(base, (int)d->src_slot_stride);
+            const int c1 = adjoint ? c1s : c1b, c2 = adjoint ? c2s : c2b;
+            so = ((c1 << n) + c2) * d->P_in;
+            sys = adjoint ? d->P_in : (d->P_in << my0);
+            ssd = 1;
+            sE = d->E_in;
+        } else {
+            rs_src = make_rsrc(reinterpret_cast<const T*>(d->vsrc[fm.group]), N * N * N);
+            so = fm.base + fm.sx * c1b + fm.sy * c2b;
+            sys = fm.sy * (1 << my0);
+            ssd = fm.sd;
+            sE = N;
+        }
+        if (d->dst_mode == 0) {
+            T* base = reinterpret_cast<T*>(d->dst) + d->dphys[slot] * d->dst_slot_stride;
+            rs_dst = make_rsrc(base, (int)d->dst_slot_stride);
+            const int c1 = adjoint ? c1b : c1s, c2 = adjoint ? c2b : c2s;
+            do_ = ((c1 << n) + c2) * d->P_out;
+            dys = adjoint ? (d->P_out << my0) : d->P_out;
+            dsd = 1;
+            dE = d->E_out;
+        } else {
+            rs_dst = make_rsrc(reinterpret_cast<T*>(d->vdst[fm.group]), N * N * N);
+            do_ = fm.base + fm.sx * c1b + fm.sy * c2b;
+            dys = fm.sy * (1 << my0);
+            dsd = fm.sd;
+            dE = N;
+        }
+        const int accum = d->dst_mode == 1 && d->accum[slot];
+        const int q0 = adjoint ? 0 : H;
+
+        // zero pads
+        for (int p = wave; p <= NS; p += NW)
+            if (lane < pad) lds[p * Lp + lane] = zero_of<T>();
+
+        uint32_t v[SPW][NCH];
+        uint32_t carry[SPW];
+#pragma unroll
+        for (int i = 0; i < SPW; ++i) carry[i] = 0u;
+
+        // columns run with unit stride, up or down (ssd, dsd = +-1): byte
+        // offsets advance by +-256 per 64-element chunk, no multiplies
+        auto issue_loads = [&](int d0) {
+#pragma unroll
+            for (int i = 0; i < SPW; ++i) {
+                const int py = py_of<KX>(wave, i);
+                const int y = adjoint ? bitrev(py, KY) : py;
+                const int dd0 = adjoint ? d0 : d0 - H - sx0 * px - sy0 * py;
+                const int colo = so + y * sys;
+                const int dl = dd0 + lane;
+                const int ob = 4 * colo + (ssd > 0 ? 4 * dl : -4 * dl);
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    // lanes outside the column get an offset past the resource:
+                    // the hardware returns 0 for them without touching memory
+                    const bool in = (unsigned)(dl + 64 * c) < (unsigned)sE;
+                    v[i][c] = bload(rs_src, in ? ob + (ssd > 0 ? 256 * c : -256 * c) : -1);
+                }
+            }
+        };
+
+        issue_loads(0);
+        for (int tile = 0; tile < ntiles; ++tile) {
+            const int d0 = tile * T_;
+            const bool live = !FINAL || tile < nlive;
+            if (live) {
+#pragma unroll
+                for (int i = 0; i < SPW; ++i) {
+                    T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + lane;
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) sl[64 * c] = from_bits<T>(v[i][c]);
+                }
+                __syncthreads();
+                if (tile + 1 < nlive) issue_loads(d0 + T_);
+                run_stages<T, NCH>(lds, Lp, pad, NCH, KX, KY, adjoint, wave, NW, lane);
+            }
+
+            // line-aligned store with carry (see store_tile_aligned)
+            const bool last_tile = tile + 1 == ntiles;
+#pragma unroll
+            for (int i = 0; i < SPW; ++i) {
+                const int py = py_of<KX>(wave, i);
+                const int y = adjoint ? py : bitrev(py, KY);
+                const int dd0 = adjoint ? d0 - sx0 * px - sy0 * py : d0;
+                const int colo = do_ + y * dys;
+                const int mis = dsd > 0 ? (colo & 31) : ((colo + 1) & 31);
+                auto line_floor = [&](int x) { return dsd > 0 ? x - ((mis + x) & 31) : x - ((x - mis) & 31); };
+                const int fbeg = dd0 <= 0 ? dd0 : line_floor(dd0);
+                const int fend = last_tile ? dd0 + T_ : line_floor(dd0 + T_);
+                const T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + q0 - dd0;
+                const int cnt = fend - fbeg;
+                const int fl = fbeg + lane;
+                const int ob = 4 * colo + (dsd > 0 ? 4 * fl : -4 * fl);
+#pragma unroll
+                for (int c = 0; c < NCH + 1; ++c) {
+                    const int k = 64 * c + lane;
+                    const int dd = fbeg + k;
+                    if (k < cnt && (unsigned)dd < (unsigned)dE) {
+                        T val = dd < dd0 ? from_bits<T>(carry[i]) : live ? sl[dd] : zero_of<T>();
+                        const int off = ob + (dsd > 0 ? 256 * c : -256 * c);
+                        if (accum) val += from_bits<T>(bload(rs_dst, off));
+                        bstore(rs_dst, off, to_bits(val));
+                    }
+                }
+                if (!last_tile) {
+                    const int tail = dd0 + T_ - fend;
+                    carry[i] = lane < tail && live ? to_bits(sl[fend + lane]) : 0u;
+                }
+            }
+            if (live) __syncthreads();
+        }
+    }
+}
+
+}  // namespace fast
+
+// ---------------------------------------------------------------------------
+// out[b][c][r] (+)= in[b][r][c]; 64 x 64 tiles through LDS, 256 threads.
+template <typename T>
+__global__ void __launch_bounds__(256)
+transpose_kernel(const TransDesc* __restrict__ descs, int ndesc)
+{
+    __shared__ T tile[64][65];
+    const long long wg = blockIdx.x;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].wg_begin <= wg) lo = mid; else hi = mid - 1;
+    }
+    const TransDesc& d = descs[lo];
+    long long local = wg - d.wg_begin;
+    const int tc = (int)(local % d.tiles_c);
+    local /= d.tiles_c;
+    const int tr = (int)(local % d.tiles_r);
+    const long long b = local / d.tiles_r;
+    const int R = d.R, C = d.C;
+    const long long plane = (long long)R * C;
+    const T* src = reinterpret_cast<const T*>(d.in) + b * plane;
+    T* dst = reinterpret_cast<T*>(d.out) + b * plane;
+    const int c0 = tc * 64, r0 = tr * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r = r0 + ty + 4 * i, c = c0 + tx;
+        if (r < R && c < C) tile[ty + 4 * i][tx] = src[(long long)r * C + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int c = c0 + ty + 4 * i, r = r0 + tx;
+        if (r < R && c < C) {
+            const long long o = (long long)c * R + r;
+            const T v = tile[tx][ty + 4 * i];
+            dst[o] = d.add ? dst[o] + v : v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_desc_djt(const DjtDesc* __restrict__ descs, int ndesc, long long wg)
+{
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].wg_begin <= wg) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// DJT pass: stages m0 .. m0+K-1 of eq. (15) fused. After them the plane of
+// output slopes (s1 * 2^K + A, s2 * 2^K + B) and block V is
+//   out[e1][e2] = sum_j c_j[e1 - s1*j - loc(j, A)][e2 - s2*j - loc(j, B)],
+// c_j the input plane of block V*2^K + j. Stage t of the pass shifts the second
+// half of each merged pair by its slope (the stage-t slope plus the new bit),
+// so block j collects s*j from the slope bits the pass inherits and loc(j, A)
+// from the bits it appends: every stage t with bit t of j set adds
+// ceil((A >> (K-1-t)) / 2), at most 2^K - 1 in all. The inherited part is
+// taken out by loading block j's tile at an origin lowered by s1*j rows and
+// s2*j columns; inside the LDS tile only the local shifts remain.
+template <int K>
+__device__ __forceinline__ int djt_loc(int j, int A)
+{
+    int s = 0;
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+        if ((j >> t) & 1) s += ((A >> (K - 1 - t)) + 1) >> 1;
+    return s;
+}
+
+// Rows of output per tile of a K-stage DJT pass: eight wavefronts each load
+// four new input rows per tile (2^K planes x T1 rows in all).
+constexpr int djt_rows_per_tile(int K) { return 32 >> K; }
+// 64-column chunks of an LDS row (E_out + 2^K - 1 columns), one kernel per
+// count; the largest takes N = 256.
+constexpr int kDjtChunkCounts[] = {1, 2, 3, 5, 9};
+
+// NCC: 64-column chunks of an LDS row (E_out + 2^K - 1 columns); NCO: of an
+// output row (E_out columns), NCC or NCC - 1.
+template <typename T, int K, int NCC, int NCO>
+__global__ void __launch_bounds__(512)
+djt_pass_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg)
+{
+    constexpr int NB = 1 << K, H = NB - 1, NO = NB * NB, NWV = 8;
+    constexpr int T1 = djt_rows_per_tile(K), RPW = NB * T1 / NWV;
+    constexpr int HPW = (NB * H + NWV - 1) / NWV;    // halo rows per wave
+    constexpr int OPW = NO >= NWV ? NO / NWV : 1;    // output planes per wave
+    constexpr int RSTEP = NO >= NWV ? 1 : NWV / NO;  // stride of its output rows
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (long long wg = blockIdx.x; wg < total_wg; wg += gridDim.x) {
+        const DjtDesc* d = descs + find_desc_djt(descs, ndesc, wg);
+        const long long local = wg - d->wg_begin;
+        const int grp = (int)(local % d->groups);
+        const int slot = (int)(local / d->groups);
+        const int N = d->N, m0 = d->m0, P = d->P;
+        const int Ein = d->E_in, Eout = d->E_out;
+        const int Vout = N >> (m0 + K);
+        const int V = grp % Vout;
+        const int sl = grp / Vout;
+        const int s1 = sl >> m0, s2 = sl & ((1 << m0) - 1);
+        const int R = T1 + H;                 // LDS rows per plane
+        const int cols_in = Eout + H;
+        const bool fin = d->final_stage != 0;
+        const int ntiles = d->ntiles;
+        // final tiles past the support e1 <= N-1+s1 of every output slope of
+        // the group are all zeros: no loads, no LDS
+        const int nlive = fin ? min(ntiles, (N - 1 + s1 * NB + H) / T1 + 1) : ntiles;
+
+        // input: the group's 2^K planes are consecutive in the stage buffer;
+        // stage 0 reads the volume through the frame map. Out-of-range lanes
+        // get an offset past the resource: the hardware returns 0.
+        __amdgpu_buffer_rsrc_t rs_in;
+        int ib, isx, isy, isd, Elim;
+        if (d->src_mode == 0) {
+            const long long pin = (long long)Ein * Ein;
+            const T* base = reinterpret_cast<const T*>(d->src) + slot * d->src_slot_stride +
+                            ((long long)sl * (N >> m0) + (long long)V * NB) * pin;
+            rs_in = make_rsrc(base, (int)(NB * pin));
+            ib = 0; isx = Ein; isy = 1; isd = (int)pin; Elim = Ein;
+        } else {
+            const FrameMap f = d->fm[slot];
+            rs_in = make_rsrc(reinterpret_cast<const T*>(d->src), N * N * N);
+            ib = f.base + f.sd * V * NB; isx = f.sx; isy = f.sy; isd = f.sd; Elim = N;
+        }
+        // output: the group's planes (t1, t2) = (s1*2^K + A, s2*2^K + B) lie
+        // inside 2^K runs of 2^K planes, Sout planes apart
+        const int Sout = 1 << (m0 + K);
+        const int pout = Eout * Eout;
+        const __amdgpu_buffer_rsrc_t rs_out = make_rsrc(
+            reinterpret_cast<T*>(d->dst) + slot * d->dst_slot_stride +
+                ((long long)(s1 * NB * Sout + s2 * NB) * Vout + V) * pout,
+            ((H * Sout + NB - 1) * Vout + 1) * pout);
+        const int o0 = wave % (NO >= NWV ? NWV : NO);
+        const int r0w = NO >= NWV ? 0 : wave / NO;
+
+        uint32_t v[RPW][NCC];
+        // the T1 new rows of tile `tile`: LDS rows H..H+T1-1 of every plane
+        auto issue = [&](int tile) {
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) {
+                const int q = wave + NWV * i;  // (plane j, new row r) = (q / T1, q % T1)
+                const int j = q / T1, r = q % T1;
+                const int e1 = tile * T1 - s1 * j + r;
+                const bool rin = (unsigned)e1 < (unsigned)Elim;
+                const int rowb = ib + isd * j + isx * e1;
+#pragma unroll
+                for (int t = 0; t < NCC; ++t) {
+                    const int e2 = 64 * t + lane - s2 * j - H;
+                    const bool in = rin && (unsigned)e2 < (unsigned)Elim;
+                    v[i][t] = bload(rs_in, in ? 4 * (rowb + isy * e2) : -1);
+                }
+            }
+        };
+        if (nlive > 0) issue(0);
+        for (int tile = 0; tile < ntiles; ++tile) {
+            const int e1_0 = tile * T1;
+            const int rows = min(T1, Eout - e1_0);
+            const bool live = tile < nlive;
+            if (live) {
+                // halo: the previous tile's top H rows (zeros for the first)
+                uint32_t h[HPW][NCC];
+#pragma unroll
+                for (int i = 0; i < HPW; ++i) {
+                    const int q = wave + NWV * i;  // (plane, halo row) = (q / H, q % H)
+#pragma unroll
+                    for (int t = 0; t < NCC; ++t) {
+                        const int c = 64 * t + lane;
+                        h[i][t] = tile > 0 && q < NB * H && c < cols_in
+                                      ? to_bits(lds[((q / H) * R + T1 + q % H) * P + c])
+                                      : 0u;
+                    }
+                }
+                __syncthreads();  // previous output phase and halo reads done
+#pragma unroll
+                for (int i = 0; i < HPW; ++i) {
+                    const int q = wave + NWV * i;
+#pragma unroll
+                    for (int t = 0; t < NCC; ++t) {
+                        const int c = 64 * t + lane;
+                        if (q < NB * H && c < cols_in) lds[((q / H) * R + q % H) * P + c] = from_bits<T>(h[i][t]);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < RPW; ++i) {
+                    const int q = wave + NWV * i;
+#pragma unroll
+                    for (int t = 0; t < NCC; ++t) {
+                        const int c = 64 * t + lane;
+                        if (c < cols_in) lds[((q / T1) * R + H + q % T1) * P + c] = from_bits<T>(v[i][t]);
+                    }
+                }
+                __syncthreads();
+            }
+            // outputs: each wave owns planes o = o0 + NWV * p and rows
+            // r = r0 + RSTEP * i of the tile. The loop is unrolled with every
+            // store unconditional (lanes past a row or past the last row get
+            // an offset outside the resource), so the next tile's loads can be
+            // issued half way through and waited for with the later half of
+            // the stores still in flight.
+            constexpr int RPWO = T1 / RSTEP;  // output rows per wave per plane
+#pragma unroll
+            for (int p = 0; p < OPW; ++p) {
+                const int o = o0 + NWV * p;
+                const int A = o >> K, B = o & H;
+                const int t1 = s1 * NB + A;
+                const int pb = (A * Sout + B) * Vout * pout;  // plane offset inside rs_out
+                const int ccap = fin ? min(Eout, N + s2 * NB + B) : Eout;
+                int lb[NB];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) lb[j] = (j * R + H - djt_loc<K>(j, A)) * P + H - djt_loc<K>(j, B);
+#pragma unroll
+                for (int i = 0; i < RPWO; ++i) {
+                    if (p * RPWO + i == (OPW * RPWO) / 2 && live && tile + 1 < nlive) issue(tile + 1);
+                    const int r = r0w + RSTEP * i;
+                    const int e1 = e1_0 + r;
+                    // final output: rows past N-1+t1 and columns past N-1+t2 are zero
+                    const int cmax = !live || r >= rows || (fin && e1 > N - 1 + t1) ? 0 : ccap;
+                    const int ob = r < rows ? pb + e1 * Eout : -(1 << 30);
+#pragma unroll
+                    for (int t = 0; t < NCO; ++t) {
+                        const int c = 64 * t + lane;
+                        T x = zero_of<T>();
+                        if (c < cmax) {
+#pragma unroll
+                            for (int j = 0; j < NB; ++j) x += lds[lb[j] + r * P + c];
+                        }
+                        bstore(rs_out, c < Eout && ob >= 0 ? 4 * (ob + c) : -1, to_bits(x));
+                    }
+                }
+            }
+        }
+        __syncthreads();  // the next work item reuses the LDS
+    }
+}
+
+}  // namespace drt3d

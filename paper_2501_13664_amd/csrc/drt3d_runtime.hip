@@ -398,8 +398,8 @@ struct Launch {
     int kind;
     std::string name;
     int fast_kx = -1, fast_ky = -1, fast_nch = -1;  // shape-specialised DRT kernel, if any
-    int fast_final = 0;                             // ... its forward-last-pass form
-    int djt_k = 0, djt_ncc = 0;                     // DJT: stages fused per pass, LDS row chunks
+    int fast_mode = 0;                              // ... 0 forward, 1 forward last pass, 2 adjoint
+    int djt_k = 0, djt_ncc = 0, djt_nco = 0;        // DJT: stages fused per pass, LDS/output row chunks
     int first = 0, ndesc = 0;
     long long total_wg = 0;
     int persistent = 0;  // grid capped at a few work groups per CU, looping over the items
@@ -512,7 +512,8 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
                     wg += (long long)d.nslots * d.groups;
                     prog.djt.push_back(d);
                     L.djt_k = d.K;
-                    L.djt_ncc = s->shape >> 4;
+                    L.djt_ncc = (s->shape >> 4) & 15;
+                    L.djt_nco = s->shape >> 8;
                 }
             }
         }
@@ -529,14 +530,14 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
                 const DrtDesc& e = prog.drt[q];
                 // the specialised kernel addresses each region with 32-bit
                 // byte offsets: N <= 512 keeps every region below 2^31 bytes
-                same = same && e.Kx == f.Kx && e.Ky == f.Ky && e.L == f.L && e.N <= 512;
+                same = same && e.Kx == f.Kx && e.Ky == f.Ky && e.L == f.L && e.N <= 512 && e.adjoint == f.adjoint;
                 final_pass = final_pass && !e.adjoint && e.dst_mode == 0 && e.nt_store;
             }
             if (same && (f.L & 63) == 0 && drt_fast_available(f.Kx, f.Ky, f.L >> 6)) {
                 L.fast_kx = f.Kx;
                 L.fast_ky = f.Ky;
                 L.fast_nch = f.L >> 6;
-                L.fast_final = final_pass;
+                L.fast_mode = f.adjoint ? 2 : final_pass ? 1 : 0;
             }
         }
         prog.launches.push_back(L);
@@ -611,7 +612,7 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
                 return fail(DRT3D_EINVAL, "%s needs %zu bytes of LDS, the device allows %d", L.name.c_str(), L.lds,
                             di.max_lds);
             if (L.fast_kx >= 0)
-                e = launch_drt_fast(p.is_float, L.fast_kx, L.fast_ky, L.fast_nch, L.fast_final, d_drt + L.first, L.ndesc,
+                e = launch_drt_fast(p.is_float, L.fast_kx, L.fast_ky, L.fast_nch, L.fast_mode, d_drt + L.first, L.ndesc,
                                     L.total_wg, grid_for(L.total_wg, di, L.persistent), L.lds, s);
             else
                 e = launch_drt_pass(p.is_float, d_drt + L.first, L.ndesc, L.total_wg, L.block,
@@ -620,7 +621,7 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
             if (L.lds > (size_t)di.max_lds)
                 return fail(DRT3D_EINVAL, "%s needs %zu bytes of LDS, the device allows %d", L.name.c_str(), L.lds,
                             di.max_lds);
-            e = launch_djt_pass(p.is_float, L.djt_k, L.djt_ncc, d_djt + L.first, L.ndesc, L.total_wg,
+            e = launch_djt_pass(p.is_float, L.djt_k, L.djt_ncc, L.djt_nco, d_djt + L.first, L.ndesc, L.total_wg,
                                 grid_for(L.total_wg, di, L.persistent), L.lds, s);
         } else {
             e = launch_transpose(p.is_float, d_tr + L.first, L.ndesc, L.total_wg, s);
@@ -1051,7 +1052,10 @@ static int djt_steps(std::vector<Step>& steps, int N, uint32_t mask, int chunked
             snprintf(nm, sizeof nm, "djt_p%d", i + 1);
             Step s; s.kind = S_DJT; s.key = kKeyPass + i; s.name = nm;
             s.waves = 8;
-            s.shape = K | ncc << 4;
+            // output chunks: a kernel with one chunk fewer than the LDS row
+            // exists; otherwise the extra chunks are masked stores
+            const int nco = (d.E_out + 63) / 64 == ncc - 1 ? ncc - 1 : ncc;
+            s.shape = K | ncc << 4 | nco << 8;
             s.lds = (size_t)NB * (d.T1 + H) * d.P * elem;
             const double in_e = i == 0 ? (double)N * N * N : (double)djt_stage_elems(N, m0);
             const double out_e = (double)djt_stage_elems(N, m0 + K);
@@ -1079,7 +1083,7 @@ static std::string program_signature(const Program& p, void* d_area)
     sig += buf;
     for (const Launch& L : p.launches) {
         snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%d:%zu:%d.%d.%d;", L.kind, L.first, L.ndesc, L.total_wg,
-                 L.persistent, L.block, L.lds, L.fast_kx, L.fast_ky, L.fast_nch + 8 * L.fast_final);
+                 L.persistent, L.block, L.lds, L.fast_kx, L.fast_ky, L.fast_nch + 8 * L.fast_mode);
         sig += buf;
     }
     return sig;

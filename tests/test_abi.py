@@ -138,7 +138,7 @@ def test_plan_text_lists_the_launches():
     text = buf.value.decode()
     assert "drt_adj" in text and "transpose_out" not in text  # z-normal dodecants only
     n = L.drt3d_plan_text(2, 16, 0xFFF, 0, buf, len(buf))
-    assert n == 4 and buf.value.decode().count("djt_stage") == 4
+    assert n == 2 and buf.value.decode().count("djt_p") == 2  # 4 stages fused 2 + 2
     assert L.drt3d_plan_text(3, 16, 0xFFF, 0, buf, len(buf)) == EINVAL
 
 

@@ -197,3 +197,45 @@ def test_drt_int_n128_full():
     announce("drt int N=128 full")
     got = api.drt3d_forward(to_dev(vol)).cpu().numpy()
     assert np.array_equal(got, O.wrap_int32(O.rec_drt(vol)))
+
+
+def test_autotune_picks_a_valid_tuning_and_stays_exact():
+    """The autotuner times candidates on the GPU and keeps the fastest; the
+    transform under its choice is still bit-exact (int32) and within the float
+    tolerance (float32, forward + adjoint are what it timed)."""
+    api = _api()
+    import torch
+    for N, dt in ((32, torch.int32), (16, torch.float32)):
+        before = api.drt3d_tuning_string(N, dt)
+        try:
+            announce("autotune N=%d %s" % (N, dt))
+            chosen = api.drt3d_autotune(N, dt)
+            assert chosen.startswith("p=") and chosen == api.drt3d_tuning_string(N, dt)
+            if dt == torch.int32:
+                vol = workloads.uniform_int_cube(N, -99, 99, seed=77)
+                got = api.drt3d_forward(to_dev(vol)).cpu().numpy()
+                assert np.array_equal(got, O.wrap_int32(O.rec_drt(vol)))
+            else:
+                vol = workloads.normal_cube(N, seed=78)
+                got = api.drt3d_forward(to_dev(vol)).cpu().numpy()
+                nw, el = float_errors(got, O.rec_drt(vol.astype(np.float64)),
+                                      O.rec_drt(np.abs(vol).astype(np.float64)))
+                assert nw <= FLOAT_TOL and el <= FLOAT_TOL
+        finally:
+            api.drt3d_set_tuning(N, before, dt)
+
+
+def test_adjoint_float_tolerance():
+    """float32 backprojection within 1e-5 of the FP64 transpose, relative to
+    R^T(|p|)."""
+    api = _api()
+    N = 32
+    rng = np.random.default_rng(79)
+    proj = rng.standard_normal((12, N, N, 3 * N - 2)).astype(np.float32)
+    announce("adjoint f32 N=32")
+    got = api.drt3d_adjoint(to_dev(proj)).cpu().numpy()
+    ref = O.rec_adj(proj.astype(np.float64), N)
+    rabs = O.rec_adj(np.abs(proj).astype(np.float64), N)
+    nw, el = float_errors(got, ref, rabs)
+    print("adjoint N=32 normwise %.3e elementwise/R^T|p| %.3e" % (nw, el))
+    assert nw <= FLOAT_TOL and el <= FLOAT_TOL
