@@ -7,13 +7,13 @@ namespace drt3d {
 
 // ---------------------------------------------------------------------------
 // Shape-specialised kernels live in their own translation units.
-static const void* fast_kernel(int is_float, int kx, int ky, int nch, int mode)
+static const void* fast_kernel(int is_float, int kx, int ky, int nch, int mode, int waves)
 {
     if (nch < 1 || nch > 6) return nullptr;
-    if (kx == 3 && ky == 3) return drt_fast_kernel_3_3(is_float, nch, mode);
-    if (kx == 2 && ky == 2) return drt_fast_kernel_2_2(is_float, nch, mode);
-    if (kx == 3 && ky == 2) return drt_fast_kernel_3_2(is_float, nch, mode);
-    if (kx == 2 && ky == 3) return drt_fast_kernel_2_3(is_float, nch, mode);
+    if (kx == 3 && ky == 3) return drt_fast_kernel_3_3(is_float, nch, mode, waves);
+    if (kx == 2 && ky == 2) return drt_fast_kernel_2_2(is_float, nch, mode, waves);
+    if (kx == 3 && ky == 2) return drt_fast_kernel_3_2(is_float, nch, mode, waves);
+    if (kx == 2 && ky == 3) return drt_fast_kernel_2_3(is_float, nch, mode, waves);
     return nullptr;
 }
 
@@ -29,11 +29,13 @@ hipError_t set_drt_lds_limit(int is_float, size_t bytes)
     const int shapes[4][2] = {{3, 3}, {2, 2}, {3, 2}, {2, 3}};
     for (auto& sh : shapes)
         for (int nc = 1; nc <= 6; ++nc)
-            for (int mode = 0; mode < 3; ++mode) {
-                hipError_t e = hipFuncSetAttribute(fast_kernel(is_float, sh[0], sh[1], nc, mode),
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-                if (e != hipSuccess) return e;
-            }
+            for (int mode = 0; mode < 3; ++mode)
+                for (int waves : {8, 16}) {
+                    const void* k = fast_kernel(is_float, sh[0], sh[1], nc, mode, waves);
+                    if (!k) continue;
+                    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+                    if (e != hipSuccess) return e;
+                }
     if (is_float)
         return hipFuncSetAttribute(reinterpret_cast<const void*>(&drt_pass_kernel<float>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -41,15 +43,18 @@ hipError_t set_drt_lds_limit(int is_float, size_t bytes)
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-int drt_fast_available(int kx, int ky, int nch) { return fast_kernel(0, kx, ky, nch, 0) != nullptr; }
-
-hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int mode, const DrtDesc* d_descs, int ndesc,
-                           long long total_wg, int grid, size_t lds_bytes, hipStream_t s)
+int drt_fast_available(int kx, int ky, int nch, int waves)
 {
-    const void* k = fast_kernel(is_float, kx, ky, nch, mode);
+    return fast_kernel(0, kx, ky, nch, 0, waves) != nullptr;
+}
+
+hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int mode, int waves, const DrtDesc* d_descs,
+                           int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s)
+{
+    const void* k = fast_kernel(is_float, kx, ky, nch, mode, waves);
     if (!k) return hipErrorInvalidValue;
     void* args[] = {&d_descs, &ndesc, &total_wg};
-    return hipLaunchKernel(k, dim3(grid), dim3(512), args, lds_bytes, s);
+    return hipLaunchKernel(k, dim3(grid), dim3(64 * waves), args, lds_bytes, s);
 }
 
 hipError_t launch_drt_pass(int is_float, const DrtDesc* d_descs, int ndesc, long long total_wg,

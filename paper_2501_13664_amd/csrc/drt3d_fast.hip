@@ -13,31 +13,39 @@
 
 namespace drt3d {
 
-template <typename T, int MODE>
+// 64-column groups (3.3) also come with 16 wavefronts per work group
+constexpr bool kWide = DRT3D_KX == 3 && DRT3D_KY == 3;
+
+template <typename T, int MODE, int NW>
 static const void* mode_kernel(int nch)
 {
 #define DRT3D_NC(NC) \
-    if (nch == NC) return reinterpret_cast<const void*>(&fast::drt_pass_fast<T, DRT3D_KX, DRT3D_KY, NC, MODE>);
+    if (nch == NC) return reinterpret_cast<const void*>(&fast::drt_pass_fast<T, DRT3D_KX, DRT3D_KY, NC, MODE, NW>);
     DRT3D_NC(1) DRT3D_NC(2) DRT3D_NC(3) DRT3D_NC(4) DRT3D_NC(5) DRT3D_NC(6)
 #undef DRT3D_NC
     return nullptr;
 }
 
-template <typename T>
+template <typename T, int NW>
 static const void* shape_kernel(int nch, int mode)
 {
     switch (mode) {
-    case 0: return mode_kernel<T, 0>(nch);
-    case 1: return mode_kernel<T, 1>(nch);
-    case 2: return mode_kernel<T, 2>(nch);
+    case 0: return mode_kernel<T, 0, NW>(nch);
+    case 1: return mode_kernel<T, 1, NW>(nch);
+    case 2: return mode_kernel<T, 2, NW>(nch);
     default: return nullptr;
     }
 }
 
-// mode: 0 forward into a stage buffer, 1 the forward's last pass, 2 adjoint
-const void* DRT3D_CAT(drt_fast_kernel_, DRT3D_KX, DRT3D_KY)(int is_float, int nch, int mode)
+// mode: 0 forward into a stage buffer, 1 the forward's last pass, 2 adjoint;
+// waves: 8, or 16 for the 3.3 shape
+const void* DRT3D_CAT(drt_fast_kernel_, DRT3D_KX, DRT3D_KY)(int is_float, int nch, int mode, int waves)
 {
-    return is_float ? shape_kernel<float>(nch, mode) : shape_kernel<uint32_t>(nch, mode);
+    if (waves == 8) return is_float ? shape_kernel<float, 8>(nch, mode) : shape_kernel<uint32_t, 8>(nch, mode);
+    if (kWide && waves == 16)
+        return is_float ? shape_kernel<float, kWide ? 16 : 8>(nch, mode)
+                        : shape_kernel<uint32_t, kWide ? 16 : 8>(nch, mode);
+    return nullptr;
 }
 
 }  // namespace drt3d

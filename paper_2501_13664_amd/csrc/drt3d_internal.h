@@ -96,16 +96,16 @@ hipError_t launch_transpose(int is_float, const TransDesc* d_descs, int ndesc, l
 hipError_t set_drt_lds_limit(int is_float, size_t bytes);
 // Kernel handles of the shape-specialised DRT passes (one translation unit
 // per shape) and of the DJT passes.
-const void* drt_fast_kernel_3_3(int is_float, int nch, int mode);
-const void* drt_fast_kernel_2_2(int is_float, int nch, int mode);
-const void* drt_fast_kernel_3_2(int is_float, int nch, int mode);
-const void* drt_fast_kernel_2_3(int is_float, int nch, int mode);
+const void* drt_fast_kernel_3_3(int is_float, int nch, int mode, int waves);
+const void* drt_fast_kernel_2_2(int is_float, int nch, int mode, int waves);
+const void* drt_fast_kernel_3_2(int is_float, int nch, int mode, int waves);
+const void* drt_fast_kernel_2_3(int is_float, int nch, int mode, int waves);
 const void* djt_pass_kernel_ptr(int is_float, int K, int ncc, int nco);
 // Shape-specialised DRT pass kernels (eight wavefronts per work group).
 // mode: 0 forward into a stage buffer, 1 the forward's last pass (every
 // descriptor writes the caller's output), 2 adjoint.
-int drt_fast_available(int kx, int ky, int nch);
-hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int mode, const DrtDesc* d_descs, int ndesc,
-                           long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
+int drt_fast_available(int kx, int ky, int nch, int waves);
+hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int mode, int waves, const DrtDesc* d_descs,
+                           int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
 
 }  // namespace drt3d

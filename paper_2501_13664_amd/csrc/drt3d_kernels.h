@@ -588,9 +588,7 @@ drt_pass_kernel(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg
 // masked.
 namespace fast {
 
-constexpr int NW = 8;
-
-template <int KX>
+template <int KX, int NW>
 __device__ __forceinline__ int py_of(int wave, int i) { return (wave >> KX) + i * (NW >> KX); }
 
 // FINAL: the forward's last pass, whose output columns are the caller's
@@ -600,8 +598,9 @@ __device__ __forceinline__ int py_of(int wave, int i) { return (wave >> KX) + i 
 // MODE: 0 a forward pass into a stage buffer, 1 the forward's last pass
 // (FINAL), 2 an adjoint pass; fixing it at compile time drops the other
 // modes' bookkeeping from the kernel.
-template <typename T, int KX, int KY, int NCH, int MODE>
-__global__ void __launch_bounds__(512)
+// NW: wavefronts per work group (8, or 16 for the 64-column 3.3 passes).
+template <typename T, int KX, int KY, int NCH, int MODE, int NW>
+__global__ void __launch_bounds__(64 * NW, NW == 16 ? 8 : 6)
 drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 {
     constexpr bool FINAL = MODE == 1;
@@ -710,7 +709,7 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
         auto issue_loads = [&](int d0) {
 #pragma unroll
             for (int i = 0; i < SPW; ++i) {
-                const int py = py_of<KX>(wave, i);
+                const int py = py_of<KX, NW>(wave, i);
                 const int y = adjoint ? bitrev(py, KY) : py;
                 const int dd0 = adjoint ? d0 : d0 - H - sx0 * px - sy0 * py;
                 const int colo = so + y * sys;
@@ -746,7 +745,7 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
             const bool last_tile = tile + 1 == ntiles;
 #pragma unroll
             for (int i = 0; i < SPW; ++i) {
-                const int py = py_of<KX>(wave, i);
+                const int py = py_of<KX, NW>(wave, i);
                 const int y = adjoint ? py : bitrev(py, KY);
                 const int dd0 = adjoint ? d0 - sx0 * px - sy0 * py : d0;
                 const int colo = do_ + y * dys;

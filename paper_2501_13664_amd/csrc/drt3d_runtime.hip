@@ -211,7 +211,7 @@ static const MeasuredTuning kMeasured[] = {
     {6, 0, "p=3.3,3.3;lds=20480;waves=8"},     {6, 1, "p=3.3,3.3;lds=24576;waves=8"},
     {7, 0, "p=2.2,2.3,3.2;lds=12288;waves=8"}, {7, 1, "p=2.2,2.3,3.2;lds=14336;waves=8"},
     {8, 0, "p=3.3,2.3,3.2;lds=14336;waves=8"}, {8, 1, "p=2.3,3.3,3.2;lds=24576;waves=8"},
-    {9, 0, "p=3.3,3.3,3.3;lds=14336;waves=8"}, {9, 1, "p=3.3,3.3,3.3;lds=14336;waves=8"},
+    {9, 0, "p=3.3,3.3,3.3;lds=14336;waves=8"}, {9, 1, "p=3.3,3.3,3.3;lds=14336;waves=16"},
 };
 
 static Tuning default_tuning(int n, int is_float)
@@ -264,7 +264,7 @@ static bool tuning_from_string(const char* s, int n, Tuning& t)
     }
     if (r.np < 1 || sx != n || sy != n) return false;
     if (r.lds_elems < 1024 || r.lds_elems > 40960) return false;
-    if (r.waves < 1 || r.waves > 8) return false;
+    if (r.waves < 1 || r.waves > 16) return false;
     t = r;
     return true;
 }
@@ -522,7 +522,7 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
         L.block = 64 * waves;
         L.lds = lds;
         L.bytes = bytes;
-        if (s0->kind == S_DRT && L.block == 512) {
+        if (s0->kind == S_DRT && (L.block == 512 || L.block == 1024)) {
             // one shape across the launch's descriptors -> specialised kernel
             const DrtDesc& f = prog.drt[L.first];
             bool same = true, final_pass = true;
@@ -533,7 +533,7 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
                 same = same && e.Kx == f.Kx && e.Ky == f.Ky && e.L == f.L && e.N <= 512 && e.adjoint == f.adjoint;
                 final_pass = final_pass && !e.adjoint && e.dst_mode == 0 && e.nt_store;
             }
-            if (same && (f.L & 63) == 0 && drt_fast_available(f.Kx, f.Ky, f.L >> 6)) {
+            if (same && (f.L & 63) == 0 && drt_fast_available(f.Kx, f.Ky, f.L >> 6, L.block / 64)) {
                 L.fast_kx = f.Kx;
                 L.fast_ky = f.Ky;
                 L.fast_nch = f.L >> 6;
@@ -612,7 +612,7 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
                 return fail(DRT3D_EINVAL, "%s needs %zu bytes of LDS, the device allows %d", L.name.c_str(), L.lds,
                             di.max_lds);
             if (L.fast_kx >= 0)
-                e = launch_drt_fast(p.is_float, L.fast_kx, L.fast_ky, L.fast_nch, L.fast_mode, d_drt + L.first, L.ndesc,
+                e = launch_drt_fast(p.is_float, L.fast_kx, L.fast_ky, L.fast_nch, L.fast_mode, L.block / 64, d_drt + L.first, L.ndesc,
                                     L.total_wg, grid_for(L.total_wg, di, L.persistent), L.lds, s);
             else
                 e = launch_drt_pass(p.is_float, d_drt + L.first, L.ndesc, L.total_wg, L.block,
@@ -700,7 +700,7 @@ static long long lds_elems_of(int nslot, int L, int pad) { return (long long)nsl
 static int fast_max_L(const PassGeom& g)
 {
     for (int nch = 16; nch >= 1; --nch)
-        if (drt_fast_available(g.Kx, g.Ky, nch)) return 64 * nch;
+        if (drt_fast_available(g.Kx, g.Ky, nch, 8)) return 64 * nch;
     return 0;
 }
 
@@ -873,7 +873,9 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
                 d.P_out = (int)round32(d.E_out);
             }
             const int K = g.Kx + g.Ky;
-            const int waves = std::min(t.waves, std::max(1, 1 << (K - 1)));
+            int waves = std::min(t.waves, std::max(1, 1 << (K - 1)));
+            // 16 wavefronts only for the shape that has such a kernel
+            if (waves > 8 && !(g.Kx == 3 && g.Ky == 3 && drt_fast_available(3, 3, L >> 6, 16))) waves = 8;
             const size_t lds = (size_t)lds_elems_of(1 << K, L, pass_pad(g)) * elem;
             const double cols = (double)N * N;
             char nm[32];
@@ -1424,7 +1426,8 @@ static void pass_list_candidates(int n, const Tuning& base, std::vector<Tuning>&
 // Timed search over the tuning space of one size class. Objective: forward
 // time for int32, forward + adjoint time for float32 (the differentiable
 // transform runs both). Phase 1 times every pass list at two LDS budgets,
-// phase 2 every LDS budget for the three best lists, phase 3 the wave count.
+// phase 2 every LDS budget for the three best lists, phase 3 the wave count
+// (4 and 16 against the default 8; 16 exists for 3.3 passes only).
 // The adjoint's buffers are allocated here (a tuning call, not a transform).
 int drt3d_autotune(int N, int dtype, const void* vol, void* out, void* workspace, size_t workspace_bytes,
                    void* stream)
@@ -1519,9 +1522,12 @@ int drt3d_autotune(int N, int dtype, const void* vol, void* out, void* workspace
             if (rc != DRT3D_OK) break;
         }
         if (rc != DRT3D_OK) break;
-        Tuning c = best;
-        c.waves = 4;
-        rc = consider(c);
+        const Tuning b = best;
+        for (int w : {4, 16}) {
+            Tuning c = b;
+            c.waves = w;
+            if ((rc = consider(c)) != DRT3D_OK) break;
+        }
     } while (0);
     put_tuning(N, is_float, best);
     (void)hipEventDestroy(ea);
