@@ -274,6 +274,47 @@ int orc_adj_def_##SUF(const IN_T* proj, int N, unsigned mask, ACC_T* vol_out)  \
                 vol_out[((int64_t)x * N + y) * N + z] =                        \
                     orc_adj_point_##SUF(proj, N, mask, x, y, z);               \
     return 0;                                                                  \
+}                                                                              \
+/* Adjoint of eq. (13) (the backprojection of lines, Sec. 5.1): every voxel    \
+ * receives, from each selected dodecant, the sum over all slope pairs of the  \
+ * one line through it: with primed coordinates (x', y', u), the entry          \
+ * J[s1][s2][N-1 + l_{s1}(u) - x'][N-1 + l_{s2}(u) - y'].                      */\
+ACC_T orc_djt_adj_point_##SUF(const IN_T* proj, int N, unsigned mask,          \
+                              int x, int y, int z)                             \
+{                                                                              \
+    int n = ilog2_exact(N);                                                    \
+    const int64_t E = 2 * (int64_t)N - 1;                                      \
+    ACC_T acc = 0;                                                             \
+    int j = 0;                                                                 \
+    for (int k = 0; k < 12; ++k) {                                             \
+        if (!((mask >> k) & 1)) continue;                                      \
+        int o[3] = {x, y, z}, p[3] = {0, 0, 0};                                \
+        for (int i = 0; i < 3; ++i) {                                          \
+            int oo = IN_ORDER[k][i];                                           \
+            int a = (oo < 0 ? -oo : oo) - 1;                                   \
+            p[a] = axis_mirrored(k, i) ? (N - 1 - o[i]) : o[i];                \
+        }                                                                      \
+        const IN_T* P = proj + (int64_t)j * N * N * E * E;                     \
+        for (int s1 = 0; s1 < N; ++s1)                                         \
+            for (int s2 = 0; s2 < N; ++s2) {                                   \
+                int e1 = N - 1 + orc_line(n, s1, p[2]) - p[0];                 \
+                int e2 = N - 1 + orc_line(n, s2, p[2]) - p[1];                 \
+                acc += (ACC_T)P[(((int64_t)s1 * N + s2) * E + e1) * E + e2];   \
+            }                                                                  \
+        ++j;                                                                   \
+    }                                                                          \
+    return acc;                                                                \
+}                                                                              \
+/* Full DJT adjoint by the definition (gather per voxel). vol_out: [N][N][N].  */\
+int orc_djt_adj_def_##SUF(const IN_T* proj, int N, unsigned mask, ACC_T* vol_out) \
+{                                                                              \
+    if (ilog2_exact(N) < 1) return -1;                                         \
+    for (int x = 0; x < N; ++x)                                                \
+        for (int y = 0; y < N; ++y)                                            \
+            for (int z = 0; z < N; ++z)                                        \
+                vol_out[((int64_t)x * N + y) * N + z] =                        \
+                    orc_djt_adj_point_##SUF(proj, N, mask, x, y, z);           \
+    return 0;                                                                  \
 }
 
 DEFINE_DEFINITIONS(i, int32_t, int64_t)

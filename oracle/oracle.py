@@ -25,8 +25,8 @@ _lib = None
 
 __all__ = [
     "build", "line", "line_recursive", "frame_to_orig", "frame_matrix",
-    "drt_point", "djt_point", "adj_point",
-    "def_drt", "def_djt", "def_adj",
+    "drt_point", "djt_point", "adj_point", "djt_adj_point",
+    "def_drt", "def_djt", "def_adj", "def_djt_adj",
     "rec_drt", "rec_djt", "rec_adj",
     "wrap_int32", "count_dodecants",
 ]
@@ -67,10 +67,11 @@ def _load():
             f = getattr(lib, "orc_djt_point_" + suf)
             f.argtypes = [inp, c_int, c_int, c_int, c_int, c_int, c_int]
             f.restype = accty
-            f = getattr(lib, "orc_adj_point_" + suf)
-            f.argtypes = [inp, c_int, c_uint, c_int, c_int, c_int]
-            f.restype = accty
-            for name in ("drt_def", "djt_def", "adj_def", "drt_rec", "djt_rec", "adj_rec"):
+            for name in ("adj_point", "djt_adj_point"):
+                f = getattr(lib, "orc_%s_%s" % (name, suf))
+                f.argtypes = [inp, c_int, c_uint, c_int, c_int, c_int]
+                f.restype = accty
+            for name in ("drt_def", "djt_def", "adj_def", "djt_adj_def", "drt_rec", "djt_rec", "adj_rec"):
                 f = getattr(lib, "orc_%s_%s" % (name, suf))
                 f.argtypes = [inp, c_int, c_uint, acc]
                 f.restype = c_int
@@ -142,6 +143,14 @@ def adj_point(proj, N, mask, x, y, z):
     return getattr(_load(), "orc_adj_point_" + suf)(p.reshape(-1), N, mask, x, y, z)
 
 
+def djt_adj_point(proj, N, mask, x, y, z):
+    """Transpose of eq. (13) at one voxel."""
+    p, suf, _ = _prep(proj)
+    if p.size != count_dodecants(mask) * N * N * (2 * N - 1) ** 2:
+        raise ValueError("projection size does not match N and mask")
+    return getattr(_load(), "orc_djt_adj_point_" + suf)(p.reshape(-1), N, mask, x, y, z)
+
+
 def _run(name, inp, N, mask, out_shape):
     v, suf, accdt = _prep(inp)
     out = np.zeros(out_shape, dtype=accdt)
@@ -177,6 +186,14 @@ def def_adj(proj, N, mask=0xFFF):
     if proj.shape != _drt_shape(N, mask):
         raise ValueError("projection shape %s != %s" % (proj.shape, _drt_shape(N, mask)))
     return _run("adj_def", proj, N, mask, (N, N, N))
+
+
+def def_djt_adj(proj, N, mask=0xFFF):
+    """Transpose of eq. (13), gathered per voxel; [N][N][N]."""
+    proj = np.asarray(proj)
+    if proj.shape != _djt_shape(N, mask):
+        raise ValueError("projection shape %s != %s" % (proj.shape, _djt_shape(N, mask)))
+    return _run("djt_adj_def", proj, N, mask, (N, N, N))
 
 
 def rec_drt(vol, mask=0xFFF):

@@ -452,3 +452,39 @@ def test_sparse_matrix_reproduces_definition_and_adjoint():
     Rk = drt_matrix(N, 0b000100000010)
     assert np.array_equal((Rk @ f.ravel().astype(np.float64)).astype(np.int64),
                           O.def_drt(f, 0b000100000010).ravel())
+
+
+# ------------------------------------------------------------ DJT adjoint
+@pytest.mark.parametrize("N,mask", [(2, 0xFFF), (4, 0xFFF), (8, 0xFFF), (8, 0b100000100001), (16, 0x00C)])
+def test_djt_adjoint_dot_product_identity(oracle_mod, N, mask):
+    """<J f, P> = <f, J^T P> exactly in int64: the DJT adjoint is the transpose
+    of the (pinned) definition of eq. (13)."""
+    O = oracle_mod
+    rng = np.random.default_rng(N + mask)
+    f = rng.integers(-9, 9, size=(N, N, N)).astype(np.int32)
+    nd = O.count_dodecants(mask)
+    P = rng.integers(-9, 9, size=(nd, N, N, 2 * N - 1, 2 * N - 1)).astype(np.int32)
+    lhs = int((O.def_djt(f, mask).astype(np.int64) * P).sum())
+    rhs = int((f.astype(np.int64) * O.def_djt_adj(P, N, mask)).sum())
+    assert lhs == rhs
+
+
+@pytest.mark.parametrize("N", [4, 8])
+def test_djt_adjoint_of_ones_counts_lines(oracle_mod, N):
+    """Each voxel lies on exactly one line of every (dodecant, s1, s2), so the
+    backprojection of all-ones is popcount(mask) * N^2 everywhere."""
+    O = oracle_mod
+    for mask in (0xFFF, 0x0A0):
+        P = np.ones((O.count_dodecants(mask), N, N, 2 * N - 1, 2 * N - 1), dtype=np.int32)
+        assert np.all(O.def_djt_adj(P, N, mask) == O.count_dodecants(mask) * N * N)
+
+
+def test_djt_adjoint_point_and_float_route(oracle_mod):
+    O = oracle_mod
+    N = 8
+    rng = np.random.default_rng(5)
+    P = rng.integers(-50, 50, size=(12, N, N, 2 * N - 1, 2 * N - 1)).astype(np.int32)
+    full = O.def_djt_adj(P, N)
+    for (x, y, z) in [(0, 0, 0), (7, 3, 5), (N - 1, N - 1, N - 1), (2, 6, 1)]:
+        assert O.djt_adj_point(P, N, 0xFFF, x, y, z) == full[x, y, z]
+    assert np.array_equal(O.def_djt_adj(P.astype(np.float64), N), full.astype(np.float64))
