@@ -15,9 +15,9 @@ the committed rocprofv3 counter summary when it was taken on the current
 sources. `cpu_baseline` times the oracle's naive Algorithm 1 on one dodecant of
 the same cube (scaled to the job).
 
-Three further measurements ride along (skipped with --no-batched / --no-diff /
---no-djt): the batched forward of 96 float32 cubes of mixed N against
-per-volume calls; the differentiable transform (forward + backward through
+Four further measurements ride along (skipped with --no-adjoint / --no-batched /
+--no-diff / --no-djt): the adjoint of the benchmark's projections; the batched
+forward of 96 float32 cubes of mixed N against per-volume calls; the differentiable transform (forward + backward through
 autograd) of a batch of 8 float32 N=128 cubes against per-volume forward +
 adjoint calls (both check that the two ways give bit-identical results); and
 the 3D DJT of one N=128 int32 cube, with U = 12 * 8 N^3 (N-1) voxel-stage
@@ -160,6 +160,29 @@ def differentiable_speedup(api, torch, reps=5):
             "updates": U, "autograd_updates_per_s": U / (ad / 1e3)}
 
 
+def adjoint_rate(api, torch, proj, N, reps=3):
+    """The DRT adjoint (backprojection) of the benchmark's own N=512 int32
+    projections, all 12 dodecants: the same recursion run in reverse."""
+    from paper_2501_13664_amd._lib import lib
+    back = torch.empty((N, N, N), dtype=torch.int32, device="cuda")
+    ws = torch.empty(lib().drt3d_adjoint_workspace_bytes(N, 0xFFF, 0), dtype=torch.uint8, device="cuda")
+    api.drt3d_adjoint(proj, out=back, workspace=ws)
+    torch.cuda.synchronize()
+    with api.profile() as prof:
+        ms = _best_ms(torch, lambda: api.drt3d_adjoint(proj, out=back, workspace=ws), reps)
+    recs = prof.records
+    dom = max(recs, key=lambda k: recs[k][0])
+    dms, dn, dbytes = recs[dom]
+    achieved = (dbytes / dn) / (dms / dn / 1e3) / 1e9
+    U = updates(N)
+    return {"workload": "drt3d_adjoint N=%d int32, 12 dodecants, of the forward's projections" % N,
+            "ms": ms, "updates": U, "updates_per_s": U / (ms / 1e3),
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS},
+            "kernels": {k: {"ms_total": v[0], "launches": v[1], "alg_GBps": v[2] / (v[0] / 1e3) / 1e9}
+                        for k, v in recs.items()}}
+
+
 def djt_rate(api, torch, reps=3):
     """The 3D DJT of lines of one N=128 int32 cube (uniform noise in [0,3] plus
     64 segments of value 8, seed 3) over all 12 dodecants: 4D output
@@ -179,12 +202,26 @@ def djt_rate(api, torch, reps=3):
     dms, dn, dbytes = recs[dom]
     achieved = (dbytes / dn) / (dms / dn / 1e3) / 1e9
     U = 12 * 8 * N ** 3 * (N - 1)
-    return {"workload": "djt3d_forward N=128 int32, 12 dodecants, noise [0,3] + 64 segments (seed 3)",
-            "ms": ms, "updates": U, "updates_per_s": U / (ms / 1e3),
-            "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS},
-            "kernels": {k: {"ms_total": v[0], "launches": v[1], "alg_GBps": v[2] / (v[0] / 1e3) / 1e9}
-                        for k, v in recs.items()}}
+    res = {"workload": "djt3d_forward N=128 int32, 12 dodecants, noise [0,3] + 64 segments (seed 3)",
+           "ms": ms, "updates": U, "updates_per_s": U / (ms / 1e3),
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS},
+           "kernels": {k: {"ms_total": v[0], "launches": v[1], "alg_GBps": v[2] / (v[0] / 1e3) / 1e9}
+                       for k, v in recs.items()}}
+    # the transpose, backprojecting that DJT output
+    del ws
+    ws = torch.empty(lib().djt3d_adjoint_workspace_bytes(N, 0xFFF, 0), dtype=torch.uint8, device="cuda")
+    back = torch.empty((N, N, N), dtype=torch.int32, device="cuda")
+    api.djt3d_adjoint(out, out=back, workspace=ws)
+    torch.cuda.synchronize()
+    with api.profile() as prof:
+        ams = _best_ms(torch, lambda: api.djt3d_adjoint(out, out=back, workspace=ws), reps)
+    recs = prof.records
+    res["adjoint"] = {"workload": "djt3d_adjoint N=128 int32, 12 dodecants, of the forward's output",
+                      "ms": ams, "updates_per_s": U / (ams / 1e3),
+                      "kernels": {k: {"ms_total": v[0], "launches": v[1], "alg_GBps": v[2] / (v[0] / 1e3) / 1e9}
+                                  for k, v in recs.items()}}
+    return res
 
 
 def copy_calibration(torch):
@@ -209,6 +246,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-djt", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -283,6 +321,10 @@ def main():
         "hbm_alg_GBps_all_kernels": total_alg / (total_ms / 1e3) / 1e9,
         "kernels": kernels,
     }
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_rate(api, torch, out, N)
+    del ws
+    torch.cuda.empty_cache()
     if not args.no_batched:
         line["batched_vs_per_volume"] = batched_speedup(api, torch)
         torch.cuda.empty_cache()

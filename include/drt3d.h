@@ -1,7 +1,7 @@
 /*
  * drt3d.h — C ABI of the MI355X (gfx950) library for the 3D multiscale discrete
  * Radon transform of planes (DRT), the 3D discrete John transform of lines (DJT)
- * and the DRT adjoint, after Marichal-Hernandez et al., "Three-dimensional
+ * and their adjoints, after Marichal-Hernandez et al., "Three-dimensional
  * multiscale discrete Radon and John transforms" (arXiv 2501.13664).
  *
  * Conventions shared by every entry point
@@ -76,15 +76,17 @@ int drt3d_abi_version(void);
 size_t drt3d_out_elems(int N, uint32_t mask);
 /* Elements of the DJT output: popcount(mask) * N * N * (2N-1)^2; 0 if invalid. */
 size_t djt3d_out_elems(int N, uint32_t mask);
-/* Workspace bytes for drt3d_forward / djt3d_forward / drt3d_adjoint (any tuning
- * choice fits). 0 if the arguments are invalid. */
+/* Workspace bytes for drt3d_forward / djt3d_forward / drt3d_adjoint /
+ * djt3d_adjoint (any tuning choice fits). 0 if the arguments are invalid. */
 size_t drt3d_workspace_bytes(int N, uint32_t mask, int dtype);
 size_t djt3d_workspace_bytes(int N, uint32_t mask, int dtype);
 size_t drt3d_adjoint_workspace_bytes(int N, uint32_t mask, int dtype);
+size_t djt3d_adjoint_workspace_bytes(int N, uint32_t mask, int dtype);
 /* Workspace bytes for the batched variants over `count` volumes of sizes Ns[]. */
 size_t drt3d_forward_batched_workspace_bytes(int count, const int* Ns, uint32_t mask, int dtype);
 size_t djt3d_forward_batched_workspace_bytes(int count, const int* Ns, uint32_t mask, int dtype);
 size_t drt3d_adjoint_batched_workspace_bytes(int count, const int* Ns, uint32_t mask, int dtype);
+size_t djt3d_adjoint_batched_workspace_bytes(int count, const int* Ns, uint32_t mask, int dtype);
 
 /* ---- transforms ----------------------------------------------------------- */
 /* 3D DRT of planes, Algorithm 1 (stage map eq. (11)) over the dodecants of
@@ -94,7 +96,8 @@ int drt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype,
                   void* workspace, size_t workspace_bytes, void* stream);
 
 /* 3D DJT of lines, Algorithm 3 (stage map eq. (15)), driving axis z', over the
- * dodecants of `mask`. out: djt3d_out_elems(N, mask) elements, overwritten. */
+ * dodecants of `mask`. out: djt3d_out_elems(N, mask) elements, overwritten.
+ * N <= 256 (DRT3D_EUNSUPPORTED above: the output alone is 48 GiB at N = 256). */
 int djt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype,
                   void* workspace, size_t workspace_bytes, void* stream);
 
@@ -102,6 +105,17 @@ int djt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype,
  * summed over the dodecants of `mask`. proj: the drt3d_forward layout for the
  * same (N, mask); vol_out: [N][N][N], overwritten. */
 int drt3d_adjoint(const void* proj, void* vol_out, int N, uint32_t mask, int dtype,
+                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* DJT adjoint: the exact transpose of djt3d_forward for the same (N, mask),
+ * i.e. of the linear map of eq. (13) (Sec. 4.1); the paper states the DRT's
+ * adjoint only (Sec. 5.1), this one follows from the same stage-by-stage
+ * transposition. vol_out[x][y][z] = sum over the selected dodecants and slope
+ * pairs of the DJT value of the one line through the voxel that is driven along
+ * z' with those slopes. proj: the djt3d_forward layout; entries outside the
+ * support e <= N-1+s of a slope are ignored. vol_out: [N][N][N], overwritten.
+ * N <= 256. */
+int djt3d_adjoint(const void* proj, void* vol_out, int N, uint32_t mask, int dtype,
                   void* workspace, size_t workspace_bytes, void* stream);
 
 /* ---- batched variants ----------------------------------------------------- */
@@ -117,6 +131,9 @@ int djt3d_forward_batched(int count, const void* const* vols, void* const* outs,
                           const int* Ns, uint32_t mask, int dtype,
                           void* workspace, size_t workspace_bytes, void* stream);
 int drt3d_adjoint_batched(int count, const void* const* projs, void* const* vols_out,
+                          const int* Ns, uint32_t mask, int dtype,
+                          void* workspace, size_t workspace_bytes, void* stream);
+int djt3d_adjoint_batched(int count, const void* const* projs, void* const* vols_out,
                           const int* Ns, uint32_t mask, int dtype,
                           void* workspace, size_t workspace_bytes, void* stream);
 
@@ -160,7 +177,7 @@ int drt3d_pass_times(char* names /* cap x 32 chars */, double* ms, long long* la
  *   kind 1 (DJT):  g_k(N-1-e1, N-1-e2, v) = vol[base + sx*e1 + sy*e2 + sd*v].  */
 int drt3d_frame_map(int k, int N, int kind, int out[5]);
 /* Text description of the launches one call would make (op 0: drt3d_forward,
- * 1: drt3d_adjoint, 2: djt3d_forward), one line per launch:
+ * 1: drt3d_adjoint, 2: djt3d_forward, 3: djt3d_adjoint), one line per launch:
  * "name kind=<k> wg=<work groups> block=<threads> lds=<bytes> bytes=<algorithmic>".
  * Returns the number of launches, or a negative status. */
 int drt3d_plan_text(int op, int N, uint32_t mask, int dtype, char* buf, size_t cap);

@@ -14,8 +14,8 @@ import torch
 from ._lib import DRT3D_ALL, DRT3D_F32, DRT3D_I32, check, lib
 
 __all__ = [
-    "DRT3D_ALL", "drt3d_forward", "djt3d_forward", "drt3d_adjoint",
-    "drt3d_forward_batched", "djt3d_forward_batched", "drt3d_adjoint_batched",
+    "DRT3D_ALL", "drt3d_forward", "djt3d_forward", "drt3d_adjoint", "djt3d_adjoint",
+    "drt3d_forward_batched", "djt3d_forward_batched", "drt3d_adjoint_batched", "djt3d_adjoint_batched",
     "drt3d_out_shape", "djt3d_out_shape", "drt3d_autotune", "drt3d_tuning_string",
     "drt3d_set_tuning", "profile", "dodecant_count",
 ]
@@ -120,6 +120,26 @@ def drt3d_adjoint(proj: torch.Tensor, mask: int = DRT3D_ALL, out: Optional[torch
     return out
 
 
+def djt3d_adjoint(proj: torch.Tensor, mask: int = DRT3D_ALL, out: Optional[torch.Tensor] = None,
+                  workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Exact transpose of djt3d_forward: [N][N][N]."""
+    if proj.dim() != 5 or proj.shape[0] != dodecant_count(mask):
+        raise ValueError("proj must be [popcount(mask)][N][N][2N-1][2N-1]")
+    N = int(proj.shape[1])
+    if tuple(proj.shape) != djt3d_out_shape(N, mask) or not proj.is_cuda or not proj.is_contiguous():
+        raise ValueError("proj must be a contiguous device tensor of shape %s" % (djt3d_out_shape(N, mask),))
+    dt = _dtype_code(proj)
+    if out is None:
+        out = torch.empty((N, N, N), dtype=proj.dtype, device=proj.device)
+    elif tuple(out.shape) != (N, N, N) or out.dtype != proj.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous %s tensor of shape %s" % (proj.dtype, (N, N, N)))
+    need = lib().djt3d_adjoint_workspace_bytes(N, mask, dt)
+    ws = _workspace(need, proj.device, workspace)
+    check(lib().djt3d_adjoint(_ptr(proj), _ptr(out), N, mask, dt, _ptr(ws), ws.numel() * ws.element_size(),
+                              _stream(stream)))
+    return out
+
+
 def _batched(fn_name: str, ws_name: str, ins: Sequence[torch.Tensor], outs: Sequence[torch.Tensor],
              Ns: Sequence[int], mask: int, dt: int, device, workspace, stream):
     count = len(ins)
@@ -180,6 +200,25 @@ def drt3d_adjoint_batched(projs: Sequence[torch.Tensor], mask: int = DRT3D_ALL,
     if outs is None:
         outs = [torch.empty((N, N, N), dtype=projs[0].dtype, device=projs[0].device) for N in Ns]
     _batched("drt3d_adjoint_batched", "drt3d_adjoint_batched_workspace_bytes", projs, outs, Ns, mask, dt,
+             projs[0].device, workspace, stream)
+    return list(outs)
+
+
+def djt3d_adjoint_batched(projs: Sequence[torch.Tensor], mask: int = DRT3D_ALL,
+                          outs: Optional[Sequence[torch.Tensor]] = None,
+                          workspace: Optional[torch.Tensor] = None, stream=None) -> List[torch.Tensor]:
+    if not projs:
+        return []
+    Ns = []
+    for p in projs:
+        N = int(p.shape[1])
+        if tuple(p.shape) != djt3d_out_shape(N, mask) or not p.is_contiguous() or not p.is_cuda:
+            raise ValueError("each projection must be a contiguous device tensor [popcount][N][N][2N-1][2N-1]")
+        Ns.append(N)
+    dt = _dtype_code(projs[0])
+    if outs is None:
+        outs = [torch.empty((N, N, N), dtype=projs[0].dtype, device=projs[0].device) for N in Ns]
+    _batched("djt3d_adjoint_batched", "djt3d_adjoint_batched_workspace_bytes", projs, outs, Ns, mask, dt,
              projs[0].device, workspace, stream)
     return list(outs)
 

@@ -68,8 +68,17 @@ struct DjtDesc {
     int P;            // LDS row pitch (>= E_out + 2^K - 1)
     int src_mode;
     int final_stage;  // output is the caller's buffer: zero tails skipped, streamed past the caches
+    // adjoint passes (djt_adj_kernel) run a forward pass's transpose: they read
+    // `src` = that pass's outputs (the caller's projections when final_stage)
+    // and write `dst` = its inputs (per-dodecant volumes when dst_mode == 1)
+    int dst_mode;
     FrameMap fm[kMaxSlots];
 };
+
+// out[i] = (accum ? out[i] : 0) + sum over s < nparts of parts[s * n + i]
+// (the per-dodecant volumes of the DJT adjoint)
+hipError_t launch_sum_parts(int is_float, const void* parts, int nparts, void* out, long long n, int accum,
+                            hipStream_t s);
 
 // One transpose out[b][c][r] (+)= in[b][r][c], b < batches, r < R, c < C, in
 // 64 x 64 tiles; work items are (b, tile row, tile column) flattened, from
@@ -88,6 +97,7 @@ hipError_t launch_drt_pass(int is_float, const DrtDesc* d_descs, int ndesc, long
 // Output rows per tile of a K-stage DJT pass, and the 64-column chunk count
 // of the kernel that takes LDS rows of `cols` columns (0: none does).
 int djt_tile_rows(int K);
+int djt_adj_tile_rows();  // forward-output rows per DJT adjoint tile
 int djt_chunks_for(int cols);
 hipError_t launch_djt_pass(int is_float, int K, int ncc, int nco, const DjtDesc* d_descs, int ndesc,
                            long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
@@ -101,6 +111,9 @@ const void* drt_fast_kernel_2_2(int is_float, int nch, int mode, int waves);
 const void* drt_fast_kernel_3_2(int is_float, int nch, int mode, int waves);
 const void* drt_fast_kernel_2_3(int is_float, int nch, int mode, int waves);
 const void* djt_pass_kernel_ptr(int is_float, int K, int ncc, int nco);
+const void* djt_adj_kernel_ptr(int is_float, int K, int ncc);
+hipError_t launch_djt_adj(int is_float, int K, int ncc, const DjtDesc* d_descs, int ndesc, long long total_wg,
+                          int grid, size_t lds_bytes, hipStream_t s);
 // Shape-specialised DRT pass kernels (eight wavefronts per work group).
 // mode: 0 forward into a stage buffer, 1 the forward's last pass (every
 // descriptor writes the caller's output), 2 adjoint.

@@ -1021,4 +1021,149 @@ djt_pass_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg
     }
 }
 
+// ---------------------------------------------------------------------------
+// DJT adjoint pass: the transpose of djt_pass_kernel for the same (m0, K).
+// The forward writes out_{A,B}[e] = sum_j in_j[e - s*j - loc(j, .)]; its
+// transpose gathers, for e on the forward's output grid,
+//   in_j[e - s*j] = sum_{A,B} out_{A,B}[e + loc(j, A), e2 + loc(j, B)],
+// so the 4^K output planes are read on one aligned window per tile (no skew)
+// and every input row x = e - s1*j is produced whole by the one tile holding
+// e. The planes stream through LDS one at a time (the next one prefetched into
+// registers) while each thread accumulates its 2^K x (rows) x (chunks) sums.
+constexpr int kDjtAdjRows = 16;  // forward-output rows e per adjoint tile
+
+template <typename T, int K, int NCC>
+__global__ void __launch_bounds__(512)
+djt_adj_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg)
+{
+    constexpr int NB = 1 << K, H = NB - 1, NO = NB * NB, NWV = 8;
+    constexpr int T1 = kDjtAdjRows, RW = T1 / NWV;         // output-grid rows per wave
+    constexpr int WR = (T1 + H + NWV - 1) / NWV;           // window rows loaded per wave
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (long long wg = blockIdx.x; wg < total_wg; wg += gridDim.x) {
+        const DjtDesc* d = descs + find_desc_djt(descs, ndesc, wg);
+        long long local = wg - d->wg_begin;
+        const int tile = (int)(local % d->ntiles);
+        local /= d->ntiles;
+        const int grp = (int)(local % d->groups);
+        const int slot = (int)(local / d->groups);
+        const int N = d->N, m0 = d->m0, P = d->P;
+        const int Ein = d->E_in, Eout = d->E_out;
+        const int Vout = N >> (m0 + K);
+        const int V = grp % Vout;
+        const int sl = grp / Vout;
+        const int s1 = sl >> m0, s2 = sl & ((1 << m0) - 1);
+        const int e0 = tile * T1;
+        const int Sout = 1 << (m0 + K);
+        const int pout = Eout * Eout;
+        const int cols = Eout + H;  // window columns: the output row plus the largest local shift
+        const bool fin = d->final_stage != 0;
+        // the group's output planes (t1, t2) = (s1*2^K + A, s2*2^K + B)
+        const __amdgpu_buffer_rsrc_t rs_in = make_rsrc(
+            reinterpret_cast<const T*>(d->src) + slot * d->src_slot_stride +
+                ((long long)(s1 * NB * Sout + s2 * NB) * Vout + V) * pout,
+            ((H * Sout + NB - 1) * Vout + 1) * pout);
+        // final: forward-output rows past N-1+t1 are zero; a window past the
+        // support of every plane of the group contributes nothing
+        const bool zero_tile = fin && e0 > N - 1 + s1 * NB + H;
+
+        T acc[NB][RW][NCC];
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int i = 0; i < RW; ++i)
+#pragma unroll
+                for (int t = 0; t < NCC; ++t) acc[j][i][t] = zero_of<T>();
+
+        if (!zero_tile) {
+            uint32_t w[WR][NCC];
+            // window rows [e0, e0 + T1 + H) of plane o, zero past E_out
+            auto fetch = [&](int o) {
+                const int A = o >> K, B = o & H;
+                const int pb = (A * Sout + B) * Vout * pout;
+#pragma unroll
+                for (int i = 0; i < WR; ++i) {
+                    const int r = wave + NWV * i;
+                    const int e1 = e0 + r;
+                    const bool rin = r < T1 + H && e1 < Eout && !(fin && e1 > N - 1 + s1 * NB + A);
+#pragma unroll
+                    for (int t = 0; t < NCC; ++t) {
+                        const int c = 64 * t + lane;
+                        w[i][t] = bload(rs_in, rin && c < Eout ? 4 * (pb + e1 * Eout + c) : -1);
+                    }
+                }
+            };
+            fetch(0);
+            for (int o = 0; o < NO; ++o) {
+                const int A = o >> K, B = o & H;
+                if (o > 0) __syncthreads();  // the previous plane's LDS reads are done
+#pragma unroll
+                for (int i = 0; i < WR; ++i) {
+                    const int r = wave + NWV * i;
+#pragma unroll
+                    for (int t = 0; t < NCC; ++t) {
+                        const int c = 64 * t + lane;
+                        if (r < T1 + H && c < cols) lds[r * P + c] = from_bits<T>(w[i][t]);
+                    }
+                }
+                __syncthreads();
+                if (o + 1 < NO) fetch(o + 1);
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const int lj = djt_loc<K>(j, A) * P + djt_loc<K>(j, B);
+#pragma unroll
+                    for (int i = 0; i < RW; ++i) {
+                        const int r = wave + NWV * i;
+#pragma unroll
+                        for (int t = 0; t < NCC; ++t) acc[j][i][t] += lds[lj + r * P + 64 * t + lane];
+                    }
+                }
+            }
+            __syncthreads();  // the next work item reuses the LDS
+        }
+        // write in_j row x1 = e - s1*j, columns x2 = e2 - s2*j, inside E_in
+        T* dst = reinterpret_cast<T*>(d->dst);
+        const FrameMap f = d->fm[slot];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int u = V * NB + j;  // block index of plane j at stage m0
+#pragma unroll
+            for (int i = 0; i < RW; ++i) {
+                const int x1 = e0 + wave + NWV * i - s1 * j;
+                if ((unsigned)x1 >= (unsigned)Ein) continue;
+#pragma unroll
+                for (int t = 0; t < NCC; ++t) {
+                    const int x2 = 64 * t + lane - s2 * j;
+                    if ((unsigned)x2 >= (unsigned)Ein) continue;
+                    if (d->dst_mode == 0) {
+                        const long long pin = (long long)Ein * Ein;
+                        dst[slot * d->dst_slot_stride + ((long long)sl * (N >> m0) + u) * pin +
+                            (long long)x1 * Ein + x2] = acc[j][i][t];
+                    } else {
+                        // stage 0: block u is the volume slice at driving
+                        // coordinate u; this dodecant's own volume
+                        dst[slot * d->dst_slot_stride + f.base + (long long)f.sd * u + (long long)f.sx * x1 +
+                            (long long)f.sy * x2] = acc[j][i][t];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// out[i] = (accum ? out[i] : 0) + sum of the parts at i
+template <typename T>
+__global__ void __launch_bounds__(256)
+sum_parts_kernel(const T* __restrict__ parts, int nparts, T* __restrict__ out, long long n, int accum)
+{
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        T s = accum ? out[i] : zero_of<T>();
+        for (int p = 0; p < nparts; ++p) s += parts[p * n + i];
+        out[i] = s;
+    }
+}
+
 }  // namespace drt3d

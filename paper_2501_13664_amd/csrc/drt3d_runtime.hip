@@ -371,7 +371,7 @@ static int prof_flush()
 }
 
 // ------------------------------------------------------------------ programs
-enum StepKind { S_DRT = 0, S_DJT = 1, S_TRANSPOSE = 2 };
+enum StepKind { S_DRT = 0, S_DJT = 1, S_TRANSPOSE = 2, S_SUM = 3 };
 
 // Step keys: a step's position in its volume's sequence, the same for every
 // volume of a batched call (forward transposes, passes, adjoint rounds,
@@ -392,6 +392,8 @@ struct Step {
     const void* t_in = nullptr;
     void* t_out = nullptr;
     int t_R = 0, t_C = 0, t_batches = 0, t_add = 0;
+    // sum: t_out[i] = (t_add ? t_out[i] : 0) + sum over p < t_R of t_in[p * sum_n + i]
+    long long sum_n = 0;
 };
 
 struct Launch {
@@ -400,6 +402,11 @@ struct Launch {
     int fast_kx = -1, fast_ky = -1, fast_nch = -1;  // shape-specialised DRT kernel, if any
     int fast_mode = 0;                              // ... 0 forward, 1 forward last pass, 2 adjoint
     int djt_k = 0, djt_ncc = 0, djt_nco = 0;        // DJT: stages fused per pass, LDS/output row chunks
+    int djt_adj = 0;                                // DJT: the pass's transpose
+    const void* sum_in = nullptr;                   // S_SUM
+    void* sum_out = nullptr;
+    int sum_parts = 0, sum_accum = 0;
+    long long sum_n = 0;
     int first = 0, ndesc = 0;
     long long total_wg = 0;
     int persistent = 0;  // grid capped at a few work groups per CU, looping over the items
@@ -459,7 +466,7 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
     while (i < order.size()) {
         const Step* s0 = order[i];
         size_t j = i + 1;
-        if (mergeable[i])
+        if (mergeable[i] && s0->kind != S_SUM)
             while (j < order.size() && mergeable[j] && order[j]->key == s0->key && order[j]->kind == s0->kind &&
                    order[j]->shape == s0->shape)
                 ++j;
@@ -467,6 +474,13 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
         L.kind = s0->kind;
         L.name = s0->name;
         L.persistent = prog.persistent && mergeable[i];
+        if (s0->kind == S_SUM) {
+            L.sum_in = s0->t_in; L.sum_out = s0->t_out; L.sum_parts = s0->t_R; L.sum_accum = s0->t_add;
+            L.sum_n = s0->sum_n; L.bytes = s0->bytes; L.block = 256;
+            prog.launches.push_back(L);
+            i = j;
+            continue;
+        }
         if (s0->kind == S_TRANSPOSE) {
             // steps of one key write different volumes: one launch is race-free
             L.first = (int)prog.tr.size();
@@ -509,11 +523,13 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
             } else {
                 for (DjtDesc d : s->djt) {
                     d.wg_begin = wg;
-                    wg += (long long)d.nslots * d.groups;
+                    // a transposed pass takes one tile per work item
+                    wg += (long long)d.nslots * d.groups * ((s->shape >> 12) & 1 ? d.ntiles : 1);
                     prog.djt.push_back(d);
                     L.djt_k = d.K;
                     L.djt_ncc = (s->shape >> 4) & 15;
-                    L.djt_nco = s->shape >> 8;
+                    L.djt_nco = (s->shape >> 8) & 15;
+                    L.djt_adj = s->shape >> 12;
                 }
             }
         }
@@ -621,8 +637,14 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
             if (L.lds > (size_t)di.max_lds)
                 return fail(DRT3D_EINVAL, "%s needs %zu bytes of LDS, the device allows %d", L.name.c_str(), L.lds,
                             di.max_lds);
-            e = launch_djt_pass(p.is_float, L.djt_k, L.djt_ncc, L.djt_nco, d_djt + L.first, L.ndesc, L.total_wg,
-                                grid_for(L.total_wg, di, L.persistent), L.lds, s);
+            if (L.djt_adj)
+                e = launch_djt_adj(p.is_float, L.djt_k, L.djt_ncc, d_djt + L.first, L.ndesc, L.total_wg,
+                                   grid_for(L.total_wg, di, L.persistent), L.lds, s);
+            else
+                e = launch_djt_pass(p.is_float, L.djt_k, L.djt_ncc, L.djt_nco, d_djt + L.first, L.ndesc, L.total_wg,
+                                    grid_for(L.total_wg, di, L.persistent), L.lds, s);
+        } else if (L.kind == S_SUM) {
+            e = launch_sum_parts(p.is_float, L.sum_in, L.sum_parts, L.sum_out, L.sum_n, L.sum_accum, s);
         } else {
             e = launch_transpose(p.is_float, d_tr + L.first, L.ndesc, L.total_wg, s);
         }
@@ -994,16 +1016,30 @@ static void djt_buffer_elems(int N, long long& a, long long& b)
     }
 }
 
-static size_t djt_ws_volume_bytes(int N, uint32_t mask, int elem, int chunked)
+// Per-dodecant workspace of the DJT: the two stage buffers, plus (adjoint) the
+// dodecant's own N^3 volume before the dodecants are summed.
+static long long djt_per_dod_elems(int N, int adjoint)
+{
+    long long a, b;
+    djt_buffer_elems(N, a, b);
+    return a + b + (adjoint ? (long long)N * N * N : 0);
+}
+
+static size_t djt_ws_volume_bytes(int N, uint32_t mask, int elem, int chunked, int adjoint = 0)
 {
     long long a, b;
     djt_buffer_elems(N, a, b);
     const int nd = popcount12(mask);
-    const int c = chunked ? chunk_size((a + b) * elem, nd) : nd;
-    return align256((size_t)c * a * elem) + align256((size_t)c * b * elem);
+    const int c = chunked ? chunk_size(djt_per_dod_elems(N, adjoint) * elem, nd) : nd;
+    size_t bytes = align256((size_t)c * a * elem) + align256((size_t)c * b * elem);
+    if (adjoint) bytes += align256((size_t)c * N * N * N * elem);
+    return bytes;
 }
 
-static int djt_steps(std::vector<Step>& steps, int N, uint32_t mask, int chunked, const DrtIO& io)
+// Steps of one DJT forward, or of its adjoint: the same passes transposed and
+// in reverse order, each dodecant backprojected into its own volume and the
+// volumes summed into the caller's.
+static int djt_steps(std::vector<Step>& steps, int N, uint32_t mask, int chunked, const DrtIO& io, int adjoint = 0)
 {
     const int n = ilog2_exact(N);
     const int elem = 4;
@@ -1013,20 +1049,24 @@ static int djt_steps(std::vector<Step>& steps, int N, uint32_t mask, int chunked
         if ((mask >> k) & 1) dods[q++] = k;
     long long A, B;
     djt_buffer_elems(N, A, B);
-    const int chunk = chunked ? chunk_size((A + B) * elem, nd) : nd;
+    const int chunk = chunked ? chunk_size(djt_per_dod_elems(N, adjoint) * elem, nd) : nd;
     char* w = io.ws;
     void* buf[2];
     buf[0] = w; w += align256((size_t)chunk * A * elem);
-    buf[1] = w;
+    buf[1] = w; w += align256((size_t)chunk * B * elem);
+    void* vparts = w;  // adjoint: [chunk][N^3]
+    const long long nvox = (long long)N * N * N;
     const std::vector<int> ks = djt_plan(n);
     const int np = (int)ks.size();
     const long long Ef = 2LL * N - 1;
     const long long slot_out = (long long)N * N * Ef * Ef;
     for (int c0 = 0; c0 < nd; c0 += chunk) {
         const int ns = std::min(chunk, nd - c0);
-        int m0 = 0;
-        for (int i = 0; i < np; ++i) {
-            const int K = ks[i];
+        std::vector<int> m0s(np);
+        for (int i = 0, m = 0; i < np; ++i) { m0s[i] = m; m += ks[i]; }
+        for (int step = 0; step < np; ++step) {
+            const int i = adjoint ? np - 1 - step : step;  // the forward pass this step runs or transposes
+            const int K = ks[i], m0 = m0s[i];
             const int NB = 1 << K, H = NB - 1;
             DjtDesc d{};
             d.N = N; d.n = n; d.m0 = m0; d.K = K;
@@ -1035,36 +1075,63 @@ static int djt_steps(std::vector<Step>& steps, int N, uint32_t mask, int chunked
             d.P = d.E_out + H;
             const int ncc = djt_chunks_for(d.P);
             if (ncc == 0) return fail(DRT3D_EUNSUPPORTED, "the DJT is built for N <= 256 (got N = %d)", N);
-            d.T1 = djt_tile_rows(K);
+            d.T1 = adjoint ? djt_adj_tile_rows() : djt_tile_rows(K);
             d.ntiles = (d.E_out + d.T1 - 1) / d.T1;
             d.groups = (1 << (2 * m0)) * (N >> (m0 + K));
             d.nslots = ns;
             for (int s = 0; s < ns; ++s) d.fm[s] = djt_frame_map(dods[c0 + s], N);
-            if (i == 0) { d.src_mode = 1; d.src = io.in; }
-            else { d.src = buf[(i - 1) & 1]; d.src_slot_stride = (i - 1) & 1 ? B : A; }
-            if (i == np - 1) {
-                d.dst = (char*)io.out + (size_t)c0 * slot_out * elem;
-                d.dst_slot_stride = slot_out;
-                d.final_stage = 1;
+            // the forward pass i reads `in` and writes `out`; its transpose the reverse
+            const void* in_p;
+            void* out_p;
+            long long in_stride, out_stride;
+            if (i == 0) { in_p = io.in; in_stride = 0; }
+            else { in_p = buf[(i - 1) & 1]; in_stride = (i - 1) & 1 ? B : A; }
+            if (i == np - 1) { out_p = (char*)io.out + (size_t)c0 * slot_out * elem; out_stride = slot_out; }
+            else { out_p = buf[i & 1]; out_stride = i & 1 ? B : A; }
+            if (adjoint) {
+                // reads what the forward pass writes (the caller's projections
+                // for the last), writes what it reads (each dodecant's own
+                // volume for the first)
+                d.src = i == np - 1 ? (const char*)io.in + (size_t)c0 * slot_out * elem : out_p;
+                d.src_slot_stride = out_stride;
+                if (i == 0) {
+                    d.dst_mode = 1;
+                    d.dst = vparts;
+                    d.dst_slot_stride = nvox;
+                } else {
+                    d.dst = const_cast<void*>(in_p);
+                    d.dst_slot_stride = in_stride;
+                }
+                d.final_stage = i == np - 1;
             } else {
-                d.dst = buf[i & 1];
-                d.dst_slot_stride = i & 1 ? B : A;
+                d.src_mode = i == 0;
+                d.src = in_p;
+                d.src_slot_stride = in_stride;
+                d.dst = out_p;
+                d.dst_slot_stride = out_stride;
+                d.final_stage = i == np - 1;
             }
             char nm[32];
-            snprintf(nm, sizeof nm, "djt_p%d", i + 1);
-            Step s; s.kind = S_DJT; s.key = kKeyPass + i; s.name = nm;
-            s.waves = 8;
+            snprintf(nm, sizeof nm, adjoint ? "djt_adj_p%d" : "djt_p%d", i + 1);
+            Step st; st.kind = S_DJT; st.key = kKeyPass + step; st.name = nm;
+            st.waves = 8;
             // output chunks: a kernel with one chunk fewer than the LDS row
             // exists; otherwise the extra chunks are masked stores
             const int nco = (d.E_out + 63) / 64 == ncc - 1 ? ncc - 1 : ncc;
-            s.shape = K | ncc << 4 | nco << 8;
-            s.lds = (size_t)NB * (d.T1 + H) * d.P * elem;
+            st.shape = K | ncc << 4 | nco << 8 | adjoint << 12;
+            st.lds = adjoint ? ((size_t)(d.T1 + H) * d.P + 128) * elem  // one plane window + spare reads
+                             : (size_t)NB * (d.T1 + H) * d.P * elem;
             const double in_e = i == 0 ? (double)N * N * N : (double)djt_stage_elems(N, m0);
             const double out_e = (double)djt_stage_elems(N, m0 + K);
-            s.bytes = (double)ns * elem * (in_e + out_e);
-            s.djt.push_back(d);
-            steps.push_back(s);
-            m0 += K;
+            st.bytes = (double)ns * elem * (in_e + out_e);
+            st.djt.push_back(d);
+            steps.push_back(st);
+        }
+        if (adjoint) {
+            Step st; st.kind = S_SUM; st.key = kKeyCombine; st.name = "djt_adj_sum";
+            st.t_in = vparts; st.t_out = io.out; st.t_R = ns; st.t_add = c0 > 0; st.sum_n = nvox;
+            st.bytes = (double)(ns + 1 + (c0 > 0)) * nvox * elem;
+            steps.push_back(st);
         }
     }
     return DRT3D_OK;
@@ -1084,9 +1151,14 @@ static std::string program_signature(const Program& p, void* d_area)
     snprintf(buf, sizeof buf, "%p|%d|", d_area, p.is_float);
     sig += buf;
     for (const Launch& L : p.launches) {
-        snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%d:%zu:%d.%d.%d;", L.kind, L.first, L.ndesc, L.total_wg,
-                 L.persistent, L.block, L.lds, L.fast_kx, L.fast_ky, L.fast_nch + 8 * L.fast_mode);
+        snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%d:%zu:%d.%d.%d:%d%d%d%d;", L.kind, L.first, L.ndesc, L.total_wg,
+                 L.persistent, L.block, L.lds, L.fast_kx, L.fast_ky, L.fast_nch + 8 * L.fast_mode, L.djt_k, L.djt_ncc,
+                 L.djt_nco, L.djt_adj);
         sig += buf;
+        if (L.kind == S_SUM) {
+            snprintf(buf, sizeof buf, "%p>%p:%d:%d:%lld;", L.sum_in, L.sum_out, L.sum_parts, L.sum_accum, L.sum_n);
+            sig += buf;
+        }
     }
     return sig;
 }
@@ -1157,15 +1229,13 @@ static int check_ws(void* ws, size_t have, size_t need)
 }
 
 // Descriptor area bounds: one DrtDesc/DjtDesc per step, per volume.
-static size_t desc_area_bytes(int kind, int N, uint32_t mask, int chunked)
+static size_t desc_area_bytes(int kind, int N, uint32_t mask, int chunked, int adjoint = 0)
 {
     const int nd = popcount12(mask);
     const int n = ilog2_exact(N);
     size_t cnt;
     if (kind == S_DJT) {
-        long long A, B;
-        djt_buffer_elems(N, A, B);
-        const int c = chunked ? chunk_size((A + B) * 4, nd) : nd;
+        const int c = chunked ? chunk_size(djt_per_dod_elems(N, adjoint) * 4, nd) : nd;
         cnt = (size_t)((nd + c - 1) / c) * n;
         return align256(cnt * sizeof(DjtDesc)) + 256;
     }
@@ -1215,14 +1285,21 @@ size_t djt3d_workspace_bytes(int N, uint32_t mask, int dtype)
     return desc_area_bytes(S_DJT, N, mask, 1) + djt_ws_volume_bytes(N, mask, 4, 1);
 }
 
+size_t djt3d_adjoint_workspace_bytes(int N, uint32_t mask, int dtype)
+{
+    if (check_common(N, mask, dtype) != DRT3D_OK) return 0;
+    return desc_area_bytes(S_DJT, N, mask, 1, 1) + djt_ws_volume_bytes(N, mask, 4, 1, 1);
+}
+
 static size_t batched_ws(int kind, int adjoint, int count, const int* Ns, uint32_t mask, int dtype)
 {
     if (count < 1 || !Ns) return 0;
     size_t d = 0, v = 0;
     for (int i = 0; i < count; ++i) {
         if (check_common(Ns[i], mask, dtype) != DRT3D_OK) return 0;
-        d += desc_area_bytes(kind, Ns[i], mask, 0);
-        v += kind == S_DJT ? djt_ws_volume_bytes(Ns[i], mask, 4, 0) : drt_ws_volume_bytes(Ns[i], mask, 4, adjoint, 0);
+        d += desc_area_bytes(kind, Ns[i], mask, 0, adjoint);
+        v += kind == S_DJT ? djt_ws_volume_bytes(Ns[i], mask, 4, 0, adjoint)
+                           : drt_ws_volume_bytes(Ns[i], mask, 4, adjoint, 0);
     }
     return align256(d) + v;
 }
@@ -1238,6 +1315,10 @@ size_t drt3d_adjoint_batched_workspace_bytes(int count, const int* Ns, uint32_t 
 size_t djt3d_forward_batched_workspace_bytes(int count, const int* Ns, uint32_t mask, int dtype)
 {
     return batched_ws(S_DJT, 0, count, Ns, mask, dtype);
+}
+size_t djt3d_adjoint_batched_workspace_bytes(int count, const int* Ns, uint32_t mask, int dtype)
+{
+    return batched_ws(S_DJT, 1, count, Ns, mask, dtype);
 }
 
 // One volume, DRT forward or adjoint.
@@ -1276,22 +1357,38 @@ int drt3d_adjoint(const void* proj, void* vol_out, int N, uint32_t mask, int dty
     return drt_single(proj, vol_out, N, mask, dtype, workspace, workspace_bytes, stream, 1);
 }
 
-int djt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype, void* workspace,
-                  size_t workspace_bytes, void* stream)
+// One volume, DJT forward or adjoint.
+static int djt_single(const void* in, void* out, int N, uint32_t mask, int dtype, void* ws, size_t ws_bytes,
+                      void* stream, int adjoint)
 {
     TRY(check_common(N, mask, dtype));
-    TRY(check_ptr(vol, "vol"));
-    TRY(check_ptr(out, "out"));
-    TRY(check_ws(workspace, workspace_bytes, djt3d_workspace_bytes(N, mask, dtype)));
+    TRY(check_ptr(in, adjoint ? "proj" : "vol"));
+    TRY(check_ptr(out, adjoint ? "vol_out" : "out"));
+    const size_t need = adjoint ? djt3d_adjoint_workspace_bytes(N, mask, dtype) : djt3d_workspace_bytes(N, mask, dtype);
+    TRY(check_ws(ws, ws_bytes, need));
     DeviceInfo di;
     TRY(device_info(di));
-    DrtIO io{vol, out, (char*)workspace + desc_area_bytes(S_DJT, N, mask, 1)};
+    DrtIO io{in, out, (char*)ws + desc_area_bytes(S_DJT, N, mask, 1, adjoint)};
     std::vector<std::vector<Step>> vols(1);
-    TRY(djt_steps(vols[0], N, mask, 1, io));
+    TRY(djt_steps(vols[0], N, mask, 1, io, adjoint));
     Program prog;
     prog.is_float = dtype == DRT3D_F32;
     build_program(prog, vols, false);
-    return execute(prog, workspace, (hipStream_t)stream, di, 0);
+    if (prog.desc_bytes() > desc_area_bytes(S_DJT, N, mask, 1, adjoint))
+        return fail(DRT3D_EINVAL, "internal: descriptor area too small");
+    return execute(prog, ws, (hipStream_t)stream, di, 0);
+}
+
+int djt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype, void* workspace,
+                  size_t workspace_bytes, void* stream)
+{
+    return djt_single(vol, out, N, mask, dtype, workspace, workspace_bytes, stream, 0);
+}
+
+int djt3d_adjoint(const void* proj, void* vol_out, int N, uint32_t mask, int dtype, void* workspace,
+                  size_t workspace_bytes, void* stream)
+{
+    return djt_single(proj, vol_out, N, mask, dtype, workspace, workspace_bytes, stream, 1);
 }
 
 // Batched calls merge the launches of volumes below this size.
@@ -1312,7 +1409,7 @@ static int batched(int kind, int adjoint, int count, const void* const* ins, voi
     TRY(device_info(di));
     const int is_float = dtype == DRT3D_F32;
     size_t dsz = 0;
-    for (int i = 0; i < count; ++i) dsz += desc_area_bytes(kind, Ns[i], mask, 0);
+    for (int i = 0; i < count; ++i) dsz += desc_area_bytes(kind, Ns[i], mask, 0, adjoint);
     char* w = (char*)ws + align256(dsz);
     std::vector<std::vector<Step>> vols(count);
     std::vector<char> solo(count, 0);
@@ -1324,8 +1421,8 @@ static int batched(int kind, int adjoint, int count, const void* const* ins, voi
         solo[i] = Ns[i] >= solo_n;
         DrtIO io{ins[i], outs[i], w};
         if (kind == S_DJT) {
-            TRY(djt_steps(vols[i], Ns[i], mask, 0, io));
-            w += djt_ws_volume_bytes(Ns[i], mask, 4, 0);
+            TRY(djt_steps(vols[i], Ns[i], mask, 0, io, adjoint));
+            w += djt_ws_volume_bytes(Ns[i], mask, 4, 0, adjoint);
         } else {
             TRY(drt_steps(vols[i], Ns[i], mask, is_float, adjoint, 0, get_tuning(Ns[i], is_float), io));
             w += drt_ws_volume_bytes(Ns[i], mask, 4, adjoint, 0);
@@ -1357,6 +1454,12 @@ int djt3d_forward_batched(int count, const void* const* vols, void* const* outs,
                           int dtype, void* workspace, size_t workspace_bytes, void* stream)
 {
     return batched(S_DJT, 0, count, vols, outs, Ns, mask, dtype, workspace, workspace_bytes, stream);
+}
+
+int djt3d_adjoint_batched(int count, const void* const* projs, void* const* vols_out, const int* Ns, uint32_t mask,
+                          int dtype, void* workspace, size_t workspace_bytes, void* stream)
+{
+    return batched(S_DJT, 1, count, projs, vols_out, Ns, mask, dtype, workspace, workspace_bytes, stream);
 }
 
 // ------------------------------------------------------------------ tuning ABI
@@ -1592,13 +1695,13 @@ int drt3d_frame_map(int k, int N, int kind, int out[5])
 int drt3d_plan_text(int op, int N, uint32_t mask, int dtype, char* buf, size_t cap)
 {
     TRY(check_common(N, mask, dtype));
-    if (op < 0 || op > 2) return fail(DRT3D_EINVAL, "op must be 0, 1 or 2");
+    if (op < 0 || op > 3) return fail(DRT3D_EINVAL, "op must be 0, 1, 2 or 3");
     const int is_float = dtype == DRT3D_F32;
     // placeholder addresses: the plan's shape does not depend on them
     static char dummy[256] __attribute__((aligned(256)));
     DrtIO io{dummy, dummy, dummy};
     std::vector<std::vector<Step>> vols(1);
-    if (op == 2) TRY(djt_steps(vols[0], N, mask, 1, io));
+    if (op >= 2) TRY(djt_steps(vols[0], N, mask, 1, io, op == 3));
     else TRY(drt_steps(vols[0], N, mask, is_float, op == 1, 1, get_tuning(N, is_float), io));
     Program prog;
     prog.is_float = is_float;

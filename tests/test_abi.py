@@ -139,7 +139,12 @@ def test_plan_text_lists_the_launches():
     assert "drt_adj" in text and "transpose_out" not in text  # z-normal dodecants only
     n = L.drt3d_plan_text(2, 16, 0xFFF, 0, buf, len(buf))
     assert n == 2 and buf.value.decode().count("djt_p") == 2  # 4 stages fused 2 + 2
-    assert L.drt3d_plan_text(3, 16, 0xFFF, 0, buf, len(buf)) == EINVAL
+    # the DJT adjoint: the same passes transposed, last first, then the sum of
+    # the per-dodecant volumes
+    n = L.drt3d_plan_text(3, 16, 0xFFF, 0, buf, len(buf))
+    lines = buf.value.decode().strip().splitlines()
+    assert n == 3 and [l.split()[0] for l in lines] == ["djt_adj_p2", "djt_adj_p1", "djt_adj_sum"]
+    assert L.drt3d_plan_text(4, 16, 0xFFF, 0, buf, len(buf)) == EINVAL
 
 
 @pytest.mark.parametrize("kind", [0, 1])
