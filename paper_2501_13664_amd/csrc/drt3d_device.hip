@@ -20,12 +20,6 @@ static const void* fast_kernel(int is_float, int kx, int ky, int nch, int mode, 
 hipError_t set_drt_lds_limit(int is_float, size_t bytes)
 {
     for (int K = 1; K <= 3; ++K)
-        for (int ncc : kDjtChunkCounts) {
-            hipError_t e = hipFuncSetAttribute(djt_adj_kernel_ptr(is_float, K, ncc),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-            if (e != hipSuccess) return e;
-        }
-    for (int K = 1; K <= 3; ++K)
         for (int ncc : kDjtChunkCounts)
             for (int nco = ncc > 1 ? ncc - 1 : 1; nco <= ncc; ++nco) {
                 hipError_t e = hipFuncSetAttribute(djt_pass_kernel_ptr(is_float, K, ncc, nco),

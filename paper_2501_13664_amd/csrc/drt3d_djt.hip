@@ -77,8 +77,9 @@ hipError_t launch_djt_adj(int is_float, int K, int ncc, const DjtDesc* d_descs, 
 {
     const void* k = djt_adj_kernel_ptr(is_float, K, ncc);
     if (!k) return hipErrorInvalidValue;
+    (void)lds_bytes;  // the ring is static LDS
     void* args[] = {&d_descs, &ndesc, &total_wg};
-    return hipLaunchKernel(k, dim3(grid), dim3(512), args, lds_bytes, s);
+    return hipLaunchKernel(k, dim3(grid), dim3(512), args, 0, s);
 }
 
 hipError_t launch_sum_parts(int is_float, const void* parts, int nparts, void* out, long long n, int accum,
@@ -97,6 +98,26 @@ hipError_t launch_sum_parts(int is_float, const void* parts, int nparts, void* o
 
 int djt_tile_rows(int K) { return djt_rows_per_tile(K); }
 int djt_adj_tile_rows() { return kDjtAdjRows; }
+// static LDS of the adjoint kernel for (K, ncc): its three-window ring
+template <int K>
+static int djt_adj_ring_elems(int ncc)
+{
+    switch (ncc) {
+    case 1: return 3 * djt_adj_window<K, 1>();
+    case 2: return 3 * djt_adj_window<K, 2>();
+    case 3: return 3 * djt_adj_window<K, 3>();
+    case 5: return 3 * djt_adj_window<K, 5>();
+    case 9: return 3 * djt_adj_window<K, 9>();
+    default: return 0;
+    }
+}
+
+size_t djt_adj_lds_bytes(int K, int ncc)
+{
+    const int e = K == 1 ? djt_adj_ring_elems<1>(ncc) : K == 2 ? djt_adj_ring_elems<2>(ncc)
+                : K == 3 ? djt_adj_ring_elems<3>(ncc) : 0;
+    return (size_t)e * 4;
+}
 
 int djt_chunks_for(int cols)
 {

@@ -1028,29 +1028,69 @@ djt_pass_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg
 //   in_j[e - s*j] = sum_{A,B} out_{A,B}[e + loc(j, A), e2 + loc(j, B)],
 // so the 4^K output planes are read on one aligned window per tile (no skew)
 // and every input row x = e - s1*j is produced whole by the one tile holding
-// e. The planes stream through LDS one at a time (the next one prefetched into
-// registers) while each thread accumulates its 2^K x (rows) x (chunks) sums.
+// e. Reading those planes is the pass's whole cost (the last pass reads the
+// full projection set), so they stream through a ring of three LDS windows
+// filled by direct-to-LDS buffer loads two planes ahead of the one being
+// summed: the loads in flight hold no registers, and each plane costs one
+// barrier. Each thread accumulates its 2^K x (rows) x (chunks) sums.
 constexpr int kDjtAdjRows = 16;  // forward-output rows e per adjoint tile
+// LDS ring of one adjoint work group: three windows of (T1 + H) rows at a
+// pitch of whole 64-column chunks (every lane of a direct load lands inside
+// its row), plus room past each for the discarded reads of shifted chunks
+// and for the loads of rows a wave does not own
+template <int K, int NCC>
+constexpr int djt_adj_window() { return (kDjtAdjRows + (1 << K) - 1) * 64 * NCC + 128; }
+
+template <int VMCNT>
+__device__ __forceinline__ void wait_vm_lds_then_barrier()
+{
+    // this wave's loads older than the newest VMCNT have landed, its LDS reads
+    // are done; then every wave of the group has reached the same point
+    static_assert(VMCNT >= 0 && VMCNT < 64, "vmcnt field");
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt((VMCNT & 15) | (7 << 4) | (0 << 8) | ((VMCNT >> 4) << 14));
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
 
 template <typename T, int K, int NCC>
 __global__ void __launch_bounds__(512)
 djt_adj_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg)
 {
     constexpr int NB = 1 << K, H = NB - 1, NO = NB * NB, NWV = 8;
-    constexpr int T1 = kDjtAdjRows, RW = T1 / NWV;         // output-grid rows per wave
-    constexpr int WR = (T1 + H + NWV - 1) / NWV;           // window rows loaded per wave
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* lds = reinterpret_cast<T*>(smem_raw);
+    constexpr int T1 = kDjtAdjRows, RW = T1 / NWV;  // output-grid rows per wave
+    constexpr int WROWS = T1 + H;                   // window rows
+    constexpr int WR = (WROWS + NWV - 1) / NWV;     // window rows loaded per wave
+    constexpr int WP = 64 * NCC;                    // LDS row pitch
+    constexpr int WSZ = djt_adj_window<K, NCC>();
+    constexpr int LPP = WR * NCC;                   // direct loads per wave per plane
+    static_assert(2 * LPP < 64, "two planes in flight fit the vmcnt field");
+    typedef __attribute__((address_space(3))) void lds_void;
+    __shared__ __align__(16) uint32_t win0[WSZ];
+    __shared__ __align__(16) uint32_t win1[WSZ];
+    __shared__ __align__(16) uint32_t win2[WSZ];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (long long wg = blockIdx.x; wg < total_wg; wg += gridDim.x) {
         const DjtDesc* d = descs + find_desc_djt(descs, ndesc, wg);
         long long local = wg - d->wg_begin;
-        const int tile = (int)(local % d->ntiles);
-        local /= d->ntiles;
+        // work groups go to the XCDs round robin: eight (slot, group) pairs
+        // share each run of 8 x ntiles work groups, so the tiles of one pair
+        // (which overlap by H rows) are read through the same L2
+        const long long pairs = (long long)d->nslots * d->groups;
+        int tile;
+        if ((pairs & 7) == 0) {
+            const long long run = local / (8LL * d->ntiles);
+            const long long in_run = local - run * 8LL * d->ntiles;
+            tile = (int)(in_run >> 3);
+            local = run * 8 + (in_run & 7);
+        } else {
+            tile = (int)(local % d->ntiles);
+            local /= d->ntiles;
+        }
         const int grp = (int)(local % d->groups);
         const int slot = (int)(local / d->groups);
-        const int N = d->N, m0 = d->m0, P = d->P;
+        const int N = d->N, m0 = d->m0;
         const int Ein = d->E_in, Eout = d->E_out;
         const int Vout = N >> (m0 + K);
         const int V = grp % Vout;
@@ -1059,15 +1099,16 @@ djt_adj_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg)
         const int e0 = tile * T1;
         const int Sout = 1 << (m0 + K);
         const int pout = Eout * Eout;
-        const int cols = Eout + H;  // window columns: the output row plus the largest local shift
         const bool fin = d->final_stage != 0;
         // the group's output planes (t1, t2) = (s1*2^K + A, s2*2^K + B)
         const __amdgpu_buffer_rsrc_t rs_in = make_rsrc(
             reinterpret_cast<const T*>(d->src) + slot * d->src_slot_stride +
                 ((long long)(s1 * NB * Sout + s2 * NB) * Vout + V) * pout,
             ((H * Sout + NB - 1) * Vout + 1) * pout);
-        // final: forward-output rows past N-1+t1 are zero; a window past the
-        // support of every plane of the group contributes nothing
+        // final: forward-output rows past N-1+t1 and columns past N-1+t2 are
+        // outside every line's support (no voxel reaches them): they are not
+        // read. A window past the support of every plane of the group
+        // contributes nothing.
         const bool zero_tile = fin && e0 > N - 1 + s1 * NB + H;
 
         T acc[NB][RW][NCC];
@@ -1079,50 +1120,59 @@ djt_adj_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg)
                 for (int t = 0; t < NCC; ++t) acc[j][i][t] = zero_of<T>();
 
         if (!zero_tile) {
-            uint32_t w[WR][NCC];
-            // window rows [e0, e0 + T1 + H) of plane o, zero past E_out
-            auto fetch = [&](int o) {
+            // window rows [e0, e0 + T1 + H) of plane o into W; loads outside
+            // the plane (or its support) get an offset past the resource and
+            // land as zeros. A wave's rows past the window load into the spare
+            // room after it, so every wave issues LPP loads per plane.
+            auto issue = [&](uint32_t* W, int o) __attribute__((always_inline)) {
                 const int A = o >> K, B = o & H;
                 const int pb = (A * Sout + B) * Vout * pout;
+                const int ccap = fin ? min(Eout, N + s2 * NB + B) : Eout;
 #pragma unroll
                 for (int i = 0; i < WR; ++i) {
                     const int r = wave + NWV * i;
                     const int e1 = e0 + r;
-                    const bool rin = r < T1 + H && e1 < Eout && !(fin && e1 > N - 1 + s1 * NB + A);
+                    const bool real = r < WROWS;
+                    const bool rin = real && e1 < Eout && !(fin && e1 > N - 1 + s1 * NB + A);
 #pragma unroll
                     for (int t = 0; t < NCC; ++t) {
                         const int c = 64 * t + lane;
-                        w[i][t] = bload(rs_in, rin && c < Eout ? 4 * (pb + e1 * Eout + c) : -1);
+                        const int off = rin && c < ccap ? 4 * (pb + e1 * Eout + c) : -1;
+                        uint32_t* dst = real ? W + r * WP + 64 * t : W + WROWS * WP;
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_in, (lds_void*)dst, 4, off, 0, 0, 0);
                     }
                 }
             };
-            fetch(0);
-            for (int o = 0; o < NO; ++o) {
+            auto sum_plane = [&](const uint32_t* W, int o) __attribute__((always_inline)) {
                 const int A = o >> K, B = o & H;
-                if (o > 0) __syncthreads();  // the previous plane's LDS reads are done
-#pragma unroll
-                for (int i = 0; i < WR; ++i) {
-                    const int r = wave + NWV * i;
-#pragma unroll
-                    for (int t = 0; t < NCC; ++t) {
-                        const int c = 64 * t + lane;
-                        if (r < T1 + H && c < cols) lds[r * P + c] = from_bits<T>(w[i][t]);
-                    }
-                }
-                __syncthreads();
-                if (o + 1 < NO) fetch(o + 1);
 #pragma unroll
                 for (int j = 0; j < NB; ++j) {
-                    const int lj = djt_loc<K>(j, A) * P + djt_loc<K>(j, B);
+                    const int lj = djt_loc<K>(j, A) * WP + djt_loc<K>(j, B);
 #pragma unroll
                     for (int i = 0; i < RW; ++i) {
                         const int r = wave + NWV * i;
 #pragma unroll
-                        for (int t = 0; t < NCC; ++t) acc[j][i][t] += lds[lj + r * P + 64 * t + lane];
+                        for (int t = 0; t < NCC; ++t)
+                            acc[j][i][t] += from_bits<T>(W[lj + r * WP + 64 * t + lane]);
                     }
                 }
+            };
+            // plane o lives in window o % 3; plane o + 2 is issued into the
+            // window that plane o - 1 used, once every wave is past it
+            auto step = [&](int o, uint32_t* cur, uint32_t* nxt) __attribute__((always_inline)) {
+                if (o + 1 < NO) wait_vm_lds_then_barrier<LPP>();  // plane o + 1 may stay in flight
+                else wait_vm_lds_then_barrier<0>();
+                if (o + 2 < NO) issue(nxt, o + 2);
+                sum_plane(cur, o);
+            };
+            issue(win0, 0);
+            issue(win1, 1);
+            for (int o = 0; o < NO; o += 3) {
+                step(o, win0, win2);
+                if (o + 1 < NO) step(o + 1, win1, win0);
+                if (o + 2 < NO) step(o + 2, win2, win1);
             }
-            __syncthreads();  // the next work item reuses the LDS
+            wait_vm_lds_then_barrier<0>();  // the next work item refills the ring
         }
         // write in_j row x1 = e - s1*j, columns x2 = e2 - s2*j, inside E_in
         T* dst = reinterpret_cast<T*>(d->dst);

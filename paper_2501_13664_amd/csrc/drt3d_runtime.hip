@@ -1119,10 +1119,12 @@ static int djt_steps(std::vector<Step>& steps, int N, uint32_t mask, int chunked
             // exists; otherwise the extra chunks are masked stores
             const int nco = (d.E_out + 63) / 64 == ncc - 1 ? ncc - 1 : ncc;
             st.shape = K | ncc << 4 | nco << 8 | adjoint << 12;
-            st.lds = adjoint ? ((size_t)(d.T1 + H) * d.P + 128) * elem  // one plane window + spare reads
-                             : (size_t)NB * (d.T1 + H) * d.P * elem;
+            st.lds = adjoint ? djt_adj_lds_bytes(K, ncc) : (size_t)NB * (d.T1 + H) * d.P * elem;
             const double in_e = i == 0 ? (double)N * N * N : (double)djt_stage_elems(N, m0);
-            const double out_e = (double)djt_stage_elems(N, m0 + K);
+            // the transpose of the last pass reads only the support e <= N-1+s
+            // of each slope: (sum over s of N + s)^2 of the (2N-1)^2 entries
+            const double sup = (double)N * N + (double)N * (N - 1) / 2;
+            const double out_e = adjoint && i == np - 1 ? sup * sup : (double)djt_stage_elems(N, m0 + K);
             st.bytes = (double)ns * elem * (in_e + out_e);
             st.djt.push_back(d);
             steps.push_back(st);
