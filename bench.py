@@ -217,8 +217,13 @@ def djt_rate(api, torch, reps=3):
     with api.profile() as prof:
         ams = _best_ms(torch, lambda: api.djt3d_adjoint(out, out=back, workspace=ws), reps)
     recs = prof.records
+    dom = max(recs, key=lambda k: recs[k][0])
+    dms, dn, dbytes = recs[dom]
+    achieved = (dbytes / dn) / (dms / dn / 1e3) / 1e9
     res["adjoint"] = {"workload": "djt3d_adjoint N=128 int32, 12 dodecants, of the forward's output",
                       "ms": ams, "updates_per_s": U / (ams / 1e3),
+                      "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS},
                       "kernels": {k: {"ms_total": v[0], "launches": v[1], "alg_GBps": v[2] / (v[0] / 1e3) / 1e9}
                                   for k, v in recs.items()}}
     return res

@@ -22,9 +22,10 @@
  * DJT output (Sec. 4.1, eq. (13)): [popcount(mask)][N][N][2N-1][2N-1], element
  *   [j][s1][s2][e1][e2] = sum over u of g_k(l_{s1}(u)+N-1-e1, l_{s2}(u)+N-1-e2, u):
  *   lines driven along z' with slopes (s1,s2) over (x',y'); e = N-1-d.
- * Adjoint (Sec. 5.1, eq. (16)-(17)): vol_out[x][y][z] = sum over the selected
- *   dodecants and all slope pairs of the DRT value of the one plane through the
- *   voxel; the exact transpose of drt3d_forward (no normalisation).
+ * Adjoints (Sec. 5.1, eqs. (16)-(18)): vol_out[x][y][z] = sum over the
+ *   selected dodecants and all slope pairs of the DRT (DJT) value of the one
+ *   plane (line) through the voxel; the exact transpose of drt3d_forward
+ *   (djt3d_forward), no normalisation.
  * Arithmetic: DRT3D_I32 is int32 with two's-complement wrap (results are exact
  *   modulo 2^32, bit-identical to any exact summation order); DRT3D_F32 is
  *   float32 accumulation in the paper's recursion order.
@@ -107,14 +108,14 @@ int djt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype,
 int drt3d_adjoint(const void* proj, void* vol_out, int N, uint32_t mask, int dtype,
                   void* workspace, size_t workspace_bytes, void* stream);
 
-/* DJT adjoint: the exact transpose of djt3d_forward for the same (N, mask),
- * i.e. of the linear map of eq. (13) (Sec. 4.1); the paper states the DRT's
- * adjoint only (Sec. 5.1), this one follows from the same stage-by-stage
- * transposition. vol_out[x][y][z] = sum over the selected dodecants and slope
+/* DJT adjoint (backprojection of lines), Alg. 3 reversed with eq. (18)
+ * (Sec. 5.1), summed over the dodecants of `mask`: the exact transpose of
+ * djt3d_forward for the same (N, mask), i.e. of eq. (13), with no
+ * normalisation. vol_out[x][y][z] = sum over the selected dodecants and slope
  * pairs of the DJT value of the one line through the voxel that is driven along
  * z' with those slopes. proj: the djt3d_forward layout; entries outside the
- * support e <= N-1+s of a slope are ignored. vol_out: [N][N][N], overwritten.
- * N <= 256. */
+ * support e <= N-1+s of a slope lie on no line through the cube and are
+ * ignored. vol_out: [N][N][N], overwritten. N <= 256. */
 int djt3d_adjoint(const void* proj, void* vol_out, int N, uint32_t mask, int dtype,
                   void* workspace, size_t workspace_bytes, void* stream);
 

@@ -275,9 +275,10 @@ int orc_adj_def_##SUF(const IN_T* proj, int N, unsigned mask, ACC_T* vol_out)  \
                     orc_adj_point_##SUF(proj, N, mask, x, y, z);               \
     return 0;                                                                  \
 }                                                                              \
-/* Adjoint of eq. (13) (the backprojection of lines, Sec. 5.1): every voxel    \
- * receives, from each selected dodecant, the sum over all slope pairs of the  \
- * one line through it: with primed coordinates (x', y', u), the entry          \
+/* Adjoint of eq. (13) (the backprojection of lines, Sec. 5.1, which eq. (18)  \
+ * computes stage by stage), by its definition: every voxel receives, from     \
+ * each selected dodecant, the sum over all slope pairs of the one line        \
+ * through it: with primed coordinates (x', y', u), the entry                  \
  * J[s1][s2][N-1 + l_{s1}(u) - x'][N-1 + l_{s2}(u) - y'].                      */\
 ACC_T orc_djt_adj_point_##SUF(const IN_T* proj, int N, unsigned mask,          \
                               int x, int y, int z)                             \

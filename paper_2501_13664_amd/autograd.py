@@ -11,7 +11,7 @@ recomputing stages instead of storing the log2(N) intermediates.
 Two mutually adjoint Functions are defined so that higher derivatives work:
 the backward of ``drt3d`` is ``drt3d_backproject`` and vice versa. The DJT of
 lines (eq. (13), Sec. 4.1) gets the same pair, ``djt3d`` and
-``djt3d_backproject``, over the transpose of its stage recursion.
+``djt3d_backproject``, over its reverse recursion (eq. (18)).
 
 Volumes are float32 (int32 is accepted for the forward value but carries no
 gradient). A leading batch dimension is accepted: a [B, N, N, N] input goes

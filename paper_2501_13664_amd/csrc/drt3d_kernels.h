@@ -1022,8 +1022,8 @@ djt_pass_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg
 }
 
 // ---------------------------------------------------------------------------
-// DJT adjoint pass: the transpose of djt_pass_kernel for the same (m0, K).
-// The forward writes out_{A,B}[e] = sum_j in_j[e - s*j - loc(j, .)]; its
+// DJT adjoint pass (Sec. 5.1, eq. (18) over K stages): the transpose of
+// djt_pass_kernel for the same (m0, K). The forward writes out_{A,B}[e] = sum_j in_j[e - s*j - loc(j, .)]; its
 // transpose gathers, for e on the forward's output grid,
 //   in_j[e - s*j] = sum_{A,B} out_{A,B}[e + loc(j, A), e2 + loc(j, B)],
 // so the 4^K output planes are read on one aligned window per tile (no skew)

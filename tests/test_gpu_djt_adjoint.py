@@ -1,6 +1,6 @@
-"""GPU parity of the DJT adjoint (the transpose of eq. (13), Sec. 4.1, run as
-the DJT's stage recursion in reverse) against the oracle's definition, through
-the C ABI binding, and of its differentiable pair.
+"""GPU parity of the DJT adjoint (Sec. 5.1, eq. (18): the DJT's stage
+recursion reversed, i.e. the transpose of eq. (13)) against the oracle's
+definition, through the C ABI binding, and of its differentiable pair.
 
 int32 results are bit-exact; float32 within 1e-5 of the FP64 oracle, relative
 to J^T(|p|). Projections are random over the whole output array, so entries
