@@ -5,3 +5,4 @@ Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 it, and the two share no code.
 """
 from .oracle import *  # noqa: F401,F403
+from .inverse import *  # noqa: F401,F403
