@@ -229,6 +229,37 @@ def djt_rate(api, torch, reps=3):
     return res
 
 
+def inverse_rate(api, torch, N=128, cycles=10, reps=2):
+    """The iterative inverse (Sec. 5.2) of the 12-dodecant float32 DRT of the
+    corners-and-centre cube (value 1 on the 8 corners and the centre voxel) at
+    N = 128: `cycles` V-cycles, after the one-time eigenvalue setup."""
+    import workloads
+    f = torch.from_numpy(workloads.corners_and_centre(N).astype("float32")).cuda()
+    b = api.drt3d_forward(f)
+    from paper_2501_13664_amd._lib import lib
+    ws = torch.empty(lib().drt3d_inverse_workspace_bytes(N), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lams = api.drt3d_inverse_lambdas(N, workspace=ws)
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    out = torch.empty((N, N, N), dtype=torch.float32, device="cuda")
+    errs = {}
+    for c in (1, 2, 4, 6):
+        api.drt3d_inverse(b, c, lams=lams, out=out, workspace=ws)
+        errs[c] = float(torch.linalg.vector_norm(out - f) / torch.linalg.vector_norm(f))
+    with api.profile() as prof:
+        ms = _best_ms(torch, lambda: api.drt3d_inverse(b, cycles, lams=lams, out=out, workspace=ws), reps)
+    errs[cycles] = float(torch.linalg.vector_norm(out - f) / torch.linalg.vector_norm(f))
+    recs = prof.records
+    calls = reps + 1  # _best_ms runs one untimed call first
+    pass_ms = sum(v[0] for v in recs.values()) / calls
+    return {"workload": "drt3d_inverse N=%d float32, 12 dodecants, corners-and-centre cube, %d V-cycles" % (N, cycles),
+            "ms": ms, "ms_per_cycle": ms / cycles, "setup_ms": setup_ms, "eigenvalues": lams,
+            "relative_error_after_cycles": errs,
+            "transform_share": pass_ms / ms,
+            "kernels": {k: {"ms_per_call": v[0] / calls, "launches_per_call": v[1] / calls} for k, v in recs.items()}}
+
+
 def copy_calibration(torch):
     """Plain 1 GiB device copy, five times: the reference for the byte counters."""
     n = 1 << 28
@@ -252,6 +283,7 @@ def main():
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-djt", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-inverse", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -338,6 +370,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_djt:
         line["djt"] = djt_rate(api, torch)
+        torch.cuda.empty_cache()
+    if not args.no_inverse:
+        line["inverse"] = inverse_rate(api, torch)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(vol_np)

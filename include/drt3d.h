@@ -138,6 +138,30 @@ int djt3d_adjoint_batched(int count, const void* const* projs, void* const* vols
                           const int* Ns, uint32_t mask, int dtype,
                           void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- inverse ---------------------------------------------------------------- */
+/* Iterative inverse of the 12-dodecant DRT (Sec. 5.2), float32 only: given
+ * proj = drt3d_forward(f) for all 12 dodecants ([12][N][N][3N-2] float32),
+ * vol_out ([N][N][N] float32, overwritten) approaches f over the cycles.
+ * The scheme is Press's iterative improvement with the approximate inverse
+ * H A^T, H the 3x3x3 high-pass filter of Sec. 5.2 (borders reflected), run in
+ * multigrid V-cycles with the restriction S (Radon domain) and prolongation P
+ * (image domain) of Sec. 5.2. Each size smooths with three step sizes (the
+ * Chebyshev nodes of [L/10, L], L = 1.02 x the largest eigenvalue of
+ * H A^T A at that size) before and after its coarse correction; size 1 takes
+ * the mean of its 12 values. cycles = 0 writes zeros.
+ * lams: NULL, or the eigenvalues for sizes 2, 4, ..., N (log2 N values), as
+ * drt3d_inverse_lambdas returns them. With NULL the library computes them
+ * by power iteration (30 steps from a fixed start vector) the first time a
+ * size is used on a device, which synchronises `stream`, and keeps them for
+ * the process.
+ * Workspace: drt3d_inverse_workspace_bytes(N), 256-byte aligned. */
+size_t drt3d_inverse_workspace_bytes(int N);
+int drt3d_inverse(const void* proj, void* vol_out, int N, int cycles, const double* lams,
+                  void* workspace, size_t workspace_bytes, void* stream);
+/* The eigenvalues the inverse uses for sizes 2, 4, ..., N, written to lams
+ * (log2 N doubles); computes the missing ones (synchronises `stream`). */
+int drt3d_inverse_lambdas(int N, double* lams, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ---- tuning ----------------------------------------------------------------- */
 /* Pick the stage grouping (stages fused per pass), tile width and LDS budget
  * (hence work groups per dodecant) and the wavefronts per work group for size

@@ -16,6 +16,7 @@ from ._lib import DRT3D_ALL, DRT3D_F32, DRT3D_I32, check, lib
 __all__ = [
     "DRT3D_ALL", "drt3d_forward", "djt3d_forward", "drt3d_adjoint", "djt3d_adjoint",
     "drt3d_forward_batched", "djt3d_forward_batched", "drt3d_adjoint_batched", "djt3d_adjoint_batched",
+    "drt3d_inverse", "drt3d_inverse_lambdas",
     "drt3d_out_shape", "djt3d_out_shape", "drt3d_autotune", "drt3d_tuning_string",
     "drt3d_set_tuning", "profile", "dodecant_count",
 ]
@@ -221,6 +222,50 @@ def djt3d_adjoint_batched(projs: Sequence[torch.Tensor], mask: int = DRT3D_ALL,
     _batched("djt3d_adjoint_batched", "djt3d_adjoint_batched_workspace_bytes", projs, outs, Ns, mask, dt,
              projs[0].device, workspace, stream)
     return list(outs)
+
+
+def _inverse_workspace(N: int, device, workspace):
+    need = lib().drt3d_inverse_workspace_bytes(N)
+    if need == 0:
+        raise ValueError("the inverse takes N a power of two >= 2, got %d" % N)
+    return _workspace(need, device, workspace)
+
+
+def drt3d_inverse(proj: torch.Tensor, cycles: int = 10, lams: Optional[Sequence[float]] = None,
+                  out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """Iterative inverse (Sec. 5.2) of a 12-dodecant float32 DRT: [N][N][N].
+
+    lams: the eigenvalues for sizes 2, 4, ..., N (as drt3d_inverse_lambdas
+    returns them), or None to let the library compute and cache them."""
+    if proj.dim() != 4 or proj.dtype != torch.float32:
+        raise ValueError("proj must be a float32 [12][N][N][3N-2] tensor")
+    N = int(proj.shape[1])
+    if tuple(proj.shape) != drt3d_out_shape(N) or not proj.is_cuda or not proj.is_contiguous():
+        raise ValueError("proj must be a contiguous device tensor of shape %s" % (drt3d_out_shape(N),))
+    if out is None:
+        out = torch.empty((N, N, N), dtype=torch.float32, device=proj.device)
+    elif tuple(out.shape) != (N, N, N) or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor of shape %s" % ((N, N, N),))
+    ws = _inverse_workspace(N, proj.device, workspace)
+    n = N.bit_length() - 1
+    arr = None
+    if lams is not None:
+        if len(lams) != n:
+            raise ValueError("lams needs %d values (sizes 2 .. %d)" % (n, N))
+        arr = (ctypes.c_double * n)(*[float(v) for v in lams])
+    check(lib().drt3d_inverse(_ptr(proj), _ptr(out), N, int(cycles), arr, _ptr(ws), ws.numel() * ws.element_size(),
+                              _stream(stream)))
+    return out
+
+
+def drt3d_inverse_lambdas(N: int, device="cuda", workspace: Optional[torch.Tensor] = None, stream=None) -> List[float]:
+    """The smoother's eigenvalues for sizes 2, 4, ..., N (computed once per size)."""
+    ws = _inverse_workspace(N, device, workspace)
+    n = N.bit_length() - 1
+    arr = (ctypes.c_double * n)()
+    check(lib().drt3d_inverse_lambdas(N, arr, _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    return list(arr)
 
 
 def drt3d_autotune(N: int, dtype=torch.float32, device="cuda") -> str:

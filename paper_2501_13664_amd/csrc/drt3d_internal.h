@@ -122,4 +122,17 @@ int drt_fast_available(int kx, int ky, int nch, int waves);
 hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int mode, int waves, const DrtDesc* d_descs,
                            int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
 
+// Iterative inverse (float32): filter, residual, restriction, prolongation,
+// and the vector steps of the power iteration.
+hipError_t launch_hp_filter(const float* y, float* out, int N, float c, int accumulate, hipStream_t s);
+hipError_t launch_residual(const float* b, const float* ax, float* r, long long n, hipStream_t s);
+hipError_t launch_restrict(const float* R, float* Rc, int N, hipStream_t s);
+hipError_t launch_prolong_add(const float* e, float* x, int N, hipStream_t s);
+hipError_t launch_base_mean(const float* b12, float* x1, hipStream_t s);
+hipError_t launch_fill(float* p, float v, long long n, hipStream_t s);
+hipError_t launch_power_start(float* v, int N, hipStream_t s);
+size_t norm_scratch_bytes();
+// scratch[norm_scratch_bytes()]: ends holding |w| (a double) at its last slot
+hipError_t launch_normalize(const float* w, float* v, long long n, double* scratch, hipStream_t s);
+
 }  // namespace drt3d

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstdarg>
 #include <cstdio>
@@ -1462,6 +1463,225 @@ int djt3d_adjoint_batched(int count, const void* const* projs, void* const* vols
                           int dtype, void* workspace, size_t workspace_bytes, void* stream)
 {
     return batched(S_DJT, 1, count, projs, vols_out, Ns, mask, dtype, workspace, workspace_bytes, stream);
+}
+
+// ------------------------------------------------------------------ inverse ABI
+// Iterative inverse of the 12-dodecant DRT (Sec. 5.2): Press's iterative
+// improvement with the approximate inverse H A^T (H the printed 3x3x3
+// high-pass filter) inside multigrid V-cycles that restrict the residual with
+// S and prolong the coarse correction with P. Each level smooths with three
+// Chebyshev step sizes over [L/10, L], L = 1.02 x the largest eigenvalue of
+// H A^T A at that size (a power iteration, computed once per size and device).
+// At size 1 the coarse problem's least-squares solution is the mean.
+namespace {
+struct InvLayout {
+    int n = 0;
+    std::vector<size_t> b, x;  // per level l (size N >> l), l >= 1
+    size_t tproj = 0, tvol = 0, tvol2 = 0, tvol3 = 0, norm = 0, drt = 0, drt_bytes = 0, total = 0;
+};
+struct InvRun {
+    const float* proj;
+    float* x0;
+    char* ws;
+    InvLayout L;
+    int N;
+    std::vector<double> lam;  // per level l < n
+    hipStream_t s;
+};
+constexpr int kInvNu = 3;
+constexpr double kInvRatio = 10.0, kInvMargin = 1.02;
+constexpr int kInvPowerIters = 30;
+std::mutex g_inv_mu;
+std::map<std::pair<int, int>, double> g_inv_lam;  // (device, size) -> eigenvalue
+}  // namespace
+
+static InvLayout inv_layout(int N)
+{
+    InvLayout L;
+    L.n = ilog2_exact(N);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.b.assign(L.n + 1, 0);
+    L.x.assign(L.n + 1, 0);
+    for (int l = 1; l <= L.n; ++l) {
+        const size_t Nl = (size_t)N >> l;
+        L.b[l] = take(12 * Nl * Nl * (3 * Nl - 2) * sizeof(float));
+        L.x[l] = take(Nl * Nl * Nl * sizeof(float));
+    }
+    const size_t vol = (size_t)N * N * N * sizeof(float);
+    L.tproj = take(12 * (size_t)N * N * (3 * (size_t)N - 2) * sizeof(float));
+    L.tvol = take(vol);
+    L.tvol2 = take(vol);
+    L.tvol3 = take(vol);
+    L.norm = take(norm_scratch_bytes());
+    size_t dw = 0;
+    for (int l = 0; l < L.n; ++l) {
+        const int Nl = N >> l;
+        dw = std::max(dw, std::max(drt3d_workspace_bytes(Nl, DRT3D_ALL, DRT3D_F32),
+                                   drt3d_adjoint_workspace_bytes(Nl, DRT3D_ALL, DRT3D_F32)));
+    }
+    L.drt = take(dw);
+    L.drt_bytes = dw;
+    L.total = off;
+    return L;
+}
+
+static int check_inverse_args(int N, void* ws, size_t ws_bytes)
+{
+    if (ilog2_exact(N) < 1 || N > DRT3D_MAX_N) return fail(DRT3D_EINVAL, "N must be a power of two in [2, %d], got %d", DRT3D_MAX_N, N);
+    if (!ws || ((uintptr_t)ws & 255)) return fail(DRT3D_EINVAL, "the inverse workspace must be non-null and 256-byte aligned");
+    const size_t need = inv_layout(N).total;
+    if (ws_bytes < need) return fail(DRT3D_ENOMEM, "inverse workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return DRT3D_OK;
+}
+
+static int inv_drt(InvRun& r, int l, const float* in, float* out, int adjoint)
+{
+    return drt_single(in, out, r.N >> l, DRT3D_ALL, DRT3D_F32, r.ws + r.L.drt, r.L.drt_bytes, r.s, adjoint);
+}
+
+static float* inv_b(InvRun& r, int l) { return l == 0 ? const_cast<float*>(r.proj) : (float*)(r.ws + r.L.b[l]); }
+static float* inv_x(InvRun& r, int l) { return l == 0 ? r.x0 : (float*)(r.ws + r.L.x[l]); }
+
+// T = b_l - A x_l in the projection temporary
+static int inv_residual(InvRun& r, int l)
+{
+    const long long Nl = r.N >> l;
+    float* T = (float*)(r.ws + r.L.tproj);
+    TRY(inv_drt(r, l, inv_x(r, l), T, 0));
+    HIP_TRY(launch_residual(inv_b(r, l), T, T, 12 * Nl * Nl * (3 * Nl - 2), r.s));
+    return DRT3D_OK;
+}
+
+// x_l += c H A^T (b_l - A x_l)
+static int inv_smooth(InvRun& r, int l, float c)
+{
+    TRY(inv_residual(r, l));
+    float* V = (float*)(r.ws + r.L.tvol);
+    TRY(inv_drt(r, l, (const float*)(r.ws + r.L.tproj), V, 1));
+    HIP_TRY(launch_hp_filter(V, inv_x(r, l), r.N >> l, c, 1, r.s));
+    return DRT3D_OK;
+}
+
+static void inv_steps(double lam, double c[kInvNu])
+{
+    const double b = kInvMargin * lam, a = b / kInvRatio;
+    for (int i = 1; i <= kInvNu; ++i)
+        c[i - 1] = 1.0 / ((b + a) / 2 + (b - a) / 2 * cos((2 * i - 1) * M_PI / (2 * kInvNu)));
+}
+
+static int inv_vcycle(InvRun& r, int l)
+{
+    const int Nl = r.N >> l;
+    if (Nl == 1) {
+        HIP_TRY(launch_base_mean(inv_b(r, l), inv_x(r, l), r.s));
+        return DRT3D_OK;
+    }
+    double c[kInvNu];
+    inv_steps(r.lam[l], c);
+    for (int i = 0; i < kInvNu; ++i) TRY(inv_smooth(r, l, (float)c[i]));
+    TRY(inv_residual(r, l));
+    HIP_TRY(launch_restrict((const float*)(r.ws + r.L.tproj), inv_b(r, l + 1), Nl, r.s));
+    const long long Nc = Nl / 2;
+    HIP_TRY(launch_fill(inv_x(r, l + 1), 0.f, Nc * Nc * Nc, r.s));
+    TRY(inv_vcycle(r, l + 1));
+    HIP_TRY(launch_prolong_add(inv_x(r, l + 1), inv_x(r, l), Nl, r.s));
+    for (int i = kInvNu - 1; i >= 0; --i) TRY(inv_smooth(r, l, (float)c[i]));
+    return DRT3D_OK;
+}
+
+// Largest eigenvalue of H A^T A at size M by power iteration (synchronises).
+static int inv_power(InvRun& r, int M, double& lam)
+{
+    float* v = (float*)(r.ws + r.L.tvol2);
+    float* w1 = (float*)(r.ws + r.L.tvol);
+    float* w2 = (float*)(r.ws + r.L.tvol3);
+    float* T = (float*)(r.ws + r.L.tproj);
+    double* scratch = (double*)(r.ws + r.L.norm);
+    const long long n = (long long)M * M * M;
+    const int l = ilog2_exact(r.N) - ilog2_exact(M);
+    HIP_TRY(launch_power_start(v, M, r.s));
+    for (int it = 0; it < kInvPowerIters; ++it) {
+        TRY(inv_drt(r, l, v, T, 0));
+        TRY(inv_drt(r, l, T, w1, 1));
+        HIP_TRY(launch_hp_filter(w1, w2, M, 1.f, 0, r.s));
+        HIP_TRY(launch_normalize(w2, v, n, scratch, r.s));
+    }
+    double norm = 0;
+    HIP_TRY(hipMemcpyAsync(&norm, (const char*)scratch + norm_scratch_bytes() - sizeof(double), sizeof(double),
+                           hipMemcpyDeviceToHost, r.s));
+    HIP_TRY(hipStreamSynchronize(r.s));
+    if (!(norm > 0) || !std::isfinite(norm)) return fail(DRT3D_EHIP, "power iteration at N = %d gave %g", M, norm);
+    lam = norm;  // v was normalised before the last product: |H A^T A v| / |v| = |w2|
+    return DRT3D_OK;
+}
+
+// Every level's eigenvalue, from the cache or the power iteration.
+static int inv_lambdas(InvRun& r)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    r.lam.assign(r.L.n, 0.0);
+    for (int l = 0; l < r.L.n; ++l) {
+        const int M = r.N >> l;
+        {
+            std::lock_guard<std::mutex> lk(g_inv_mu);
+            auto it = g_inv_lam.find({dev, M});
+            if (it != g_inv_lam.end()) {
+                r.lam[l] = it->second;
+                continue;
+            }
+        }
+        double lam = 0;
+        TRY(inv_power(r, M, lam));
+        std::lock_guard<std::mutex> lk(g_inv_mu);
+        g_inv_lam[{dev, M}] = lam;
+        r.lam[l] = lam;
+    }
+    return DRT3D_OK;
+}
+
+size_t drt3d_inverse_workspace_bytes(int N)
+{
+    if (ilog2_exact(N) < 1 || N > DRT3D_MAX_N) return 0;
+    return inv_layout(N).total;
+}
+
+int drt3d_inverse_lambdas(int N, double* lams, void* workspace, size_t workspace_bytes, void* stream)
+{
+    TRY(check_inverse_args(N, workspace, workspace_bytes));
+    if (!lams) return fail(DRT3D_EINVAL, "lams must not be NULL");
+    InvRun r{nullptr, nullptr, (char*)workspace, inv_layout(N), N, {}, (hipStream_t)stream};
+    TRY(inv_lambdas(r));
+    for (int l = 0; l < r.L.n; ++l) lams[r.L.n - 1 - l] = r.lam[l];  // sizes 2, 4, ..., N
+    return DRT3D_OK;
+}
+
+int drt3d_inverse(const void* proj, void* vol_out, int N, int cycles, const double* lams, void* workspace,
+                  size_t workspace_bytes, void* stream)
+{
+    TRY(check_inverse_args(N, workspace, workspace_bytes));
+    TRY(check_ptr(proj, "proj"));
+    TRY(check_ptr(vol_out, "vol_out"));
+    if (cycles < 0) return fail(DRT3D_EINVAL, "cycles must be >= 0, got %d", cycles);
+    InvRun r{(const float*)proj, (float*)vol_out, (char*)workspace, inv_layout(N), N, {}, (hipStream_t)stream};
+    if (lams) {
+        r.lam.assign(r.L.n, 0.0);
+        for (int l = 0; l < r.L.n; ++l) {
+            const double v = lams[r.L.n - 1 - l];
+            if (!(v > 0) || !std::isfinite(v)) return fail(DRT3D_EINVAL, "lams[%d] = %g is not a positive eigenvalue", r.L.n - 1 - l, v);
+            r.lam[l] = v;
+        }
+    } else {
+        TRY(inv_lambdas(r));
+    }
+    HIP_TRY(launch_fill(r.x0, 0.f, (long long)N * N * N, r.s));
+    for (int c = 0; c < cycles; ++c) TRY(inv_vcycle(r, 0));
+    return DRT3D_OK;
 }
 
 // ------------------------------------------------------------------ tuning ABI

@@ -95,6 +95,32 @@ def test_bad_arguments_are_rejected_before_any_device_work():
         assert word in L.drt3d_last_error().decode()
 
 
+def test_inverse_argument_checks():
+    """The inverse validates N, pointers, workspace, cycles and the given
+    eigenvalues before any device work."""
+    L = _lib()
+    A = _fake(1 << 20)
+    need = L.drt3d_inverse_workspace_bytes(8)
+    assert need > 0 and L.drt3d_inverse_workspace_bytes(16) > need
+    for bad in (0, 1, 3, 12, 2048):
+        assert L.drt3d_inverse_workspace_bytes(bad) == 0
+    good = (ctypes.c_double * 3)(1.0, 2.0, 3.0)
+    bad_lams = (ctypes.c_double * 3)(1.0, -2.0, 3.0)
+    cases = [
+        (lambda: L.drt3d_inverse(A, A, 6, 1, good, A, need, None), EINVAL, "power of two"),
+        (lambda: L.drt3d_inverse(None, A, 8, 1, good, A, need, None), EINVAL, "NULL"),
+        (lambda: L.drt3d_inverse(A, None, 8, 1, good, A, need, None), EINVAL, "NULL"),
+        (lambda: L.drt3d_inverse(A, A, 8, 1, good, A, need - 1, None), ENOMEM, "too small"),
+        (lambda: L.drt3d_inverse(A, A, 8, 1, good, _fake((1 << 20) + 64), need, None), EINVAL, "256"),
+        (lambda: L.drt3d_inverse(A, A, 8, -1, good, A, need, None), EINVAL, "cycles"),
+        (lambda: L.drt3d_inverse(A, A, 8, 1, bad_lams, A, need, None), EINVAL, "eigenvalue"),
+        (lambda: L.drt3d_inverse_lambdas(8, None, A, need, None), EINVAL, "NULL"),
+    ]
+    for fn, code, word in cases:
+        assert fn() == code
+        assert word in L.drt3d_last_error().decode()
+
+
 def test_batched_argument_checks():
     L = _lib()
     A = (1 << 20)
