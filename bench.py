@@ -15,13 +15,15 @@ the committed rocprofv3 counter summary when it was taken on the current
 sources. `cpu_baseline` times the oracle's naive Algorithm 1 on one dodecant of
 the same cube (scaled to the job).
 
-Four further measurements ride along (skipped with --no-adjoint / --no-batched /
---no-diff / --no-djt): the adjoint of the benchmark's projections; the batched
-forward of 96 float32 cubes of mixed N against per-volume calls; the differentiable transform (forward + backward through
+Further measurements ride along (skipped with --no-adjoint / --no-batched /
+--no-diff / --no-djt / --no-inverse): the adjoint of the benchmark's
+projections; the batched forward of 96 float32 cubes of mixed N against
+per-volume calls; the differentiable transform (forward + backward through
 autograd) of a batch of 8 float32 N=128 cubes against per-volume forward +
-adjoint calls (both check that the two ways give bit-identical results); and
-the 3D DJT of one N=128 int32 cube, with U = 12 * 8 N^3 (N-1) voxel-stage
-updates.
+adjoint calls (both check that the two ways give bit-identical results); the
+3D DJT of one N=128 int32 cube, with U = 12 * 8 N^3 (N-1) voxel-stage updates,
+and its adjoint; and the iterative inverse of a float32 N=128 DRT (ten
+V-cycles) with its error after each cycle count.
 
 --copy-calibration runs only a plain 1 GiB device-to-device copy (five times),
 the reference kernel that scales the HBM byte counters.
@@ -45,16 +47,20 @@ def updates(N, ndod=12):
     return ndod * n * N * N * 3 * N
 
 
-SOURCES = ["paper_2501_13664_amd/csrc/drt3d_device.hip", "paper_2501_13664_amd/csrc/drt3d_runtime.hip",
-           "paper_2501_13664_amd/csrc/drt3d_internal.h"]
+CSRC = "paper_2501_13664_amd/csrc"
 
 
 def sources_sha256():
-    """One hash over the HIP sources (kernels and the launch planning)."""
+    """One hash over every HIP source and header of the library (kernels and
+    launch planning), in name order: a counter record taken on other sources
+    no longer describes the kernels that run."""
     import hashlib
     h = hashlib.sha256()
-    for rel in SOURCES:
-        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    d = os.path.join(ROOT, CSRC)
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
     return h.hexdigest()
 
 

@@ -695,7 +695,7 @@ static long long max_intermediate_extent(int N)
 // 128-byte line.
 static long long drt_stage_elems_per_dod(int N) { return (long long)N * N * round32(max_intermediate_extent(N)); }
 
-static const long long kStageBudget = 8LL << 30;  // stage-buffer bytes of one single-volume call
+static const long long kStageBudget = 16LL << 30;  // stage-buffer bytes of one single-volume call
 
 static int chunk_size(long long per_dod_bytes, int ndod)
 {
