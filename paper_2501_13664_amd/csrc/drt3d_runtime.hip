@@ -1476,8 +1476,16 @@ int djt3d_adjoint_batched(int count, const void* const* projs, void* const* vols
 namespace {
 struct InvLayout {
     int n = 0;
-    std::vector<size_t> b, x;  // per level l (size N >> l), l >= 1
+    std::vector<size_t> b, x;          // per level l (size N >> l), l >= 1
+    std::vector<size_t> dfwd, dadj;    // per level l < n: descriptor areas of its forward and adjoint
     size_t tproj = 0, tvol = 0, tvol2 = 0, tvol3 = 0, norm = 0, drt = 0, drt_bytes = 0, total = 0;
+};
+// A level's forward (x_l -> T) or adjoint (T -> V), planned once per call
+// with its descriptors uploaded once into its own area: the cycles then only
+// launch kernels.
+struct InvProg {
+    Program p;
+    char* area = nullptr;
 };
 struct InvRun {
     const float* proj;
@@ -1487,6 +1495,8 @@ struct InvRun {
     int N;
     std::vector<double> lam;  // per level l < n
     hipStream_t s;
+    std::vector<InvProg> fwd, adj;  // per level l < n, once prepared
+    DeviceInfo di;
 };
 constexpr int kInvNu = 3;
 constexpr double kInvRatio = 10.0, kInvMargin = 1.02;
@@ -1507,6 +1517,12 @@ static InvLayout inv_layout(int N)
     };
     L.b.assign(L.n + 1, 0);
     L.x.assign(L.n + 1, 0);
+    L.dfwd.assign(L.n, 0);
+    L.dadj.assign(L.n, 0);
+    for (int l = 0; l < L.n; ++l) {
+        L.dfwd[l] = take(desc_area_bytes(S_DRT, N >> l, DRT3D_ALL, 1, 0));
+        L.dadj[l] = take(desc_area_bytes(S_DRT, N >> l, DRT3D_ALL, 1, 1));
+    }
     for (int l = 1; l <= L.n; ++l) {
         const size_t Nl = (size_t)N >> l;
         L.b[l] = take(12 * Nl * Nl * (3 * Nl - 2) * sizeof(float));
@@ -1547,12 +1563,41 @@ static int inv_drt(InvRun& r, int l, const float* in, float* out, int adjoint)
 static float* inv_b(InvRun& r, int l) { return l == 0 ? const_cast<float*>(r.proj) : (float*)(r.ws + r.L.b[l]); }
 static float* inv_x(InvRun& r, int l) { return l == 0 ? r.x0 : (float*)(r.ws + r.L.x[l]); }
 
+// Plans level l's forward (x_l -> T) and adjoint (T -> V) and uploads their
+// descriptors; the stage buffers of both live in the shared transform region
+// (the calls are stream-ordered).
+static int inv_prepare(InvRun& r)
+{
+    TRY(device_info(r.di));
+    r.fwd.assign(r.L.n, InvProg{});
+    r.adj.assign(r.L.n, InvProg{});
+    for (int l = 0; l < r.L.n; ++l) {
+        const int Nl = r.N >> l;
+        const Tuning t = get_tuning(Nl, 1);
+        for (int adjoint = 0; adjoint < 2; ++adjoint) {
+            InvProg& ip = adjoint ? r.adj[l] : r.fwd[l];
+            const void* in = adjoint ? (const void*)(r.ws + r.L.tproj) : (const void*)inv_x(r, l);
+            void* out = adjoint ? (void*)(r.ws + r.L.tvol) : (void*)(r.ws + r.L.tproj);
+            DrtIO io{in, out, r.ws + r.L.drt};
+            std::vector<std::vector<Step>> vols(1);
+            TRY(drt_steps(vols[0], Nl, DRT3D_ALL, 1, adjoint, 1, t, io));
+            ip.p.is_float = 1;
+            build_program(ip.p, vols, false);
+            ip.area = r.ws + (adjoint ? r.L.dadj[l] : r.L.dfwd[l]);
+            if (ip.p.desc_bytes() > desc_area_bytes(S_DRT, Nl, DRT3D_ALL, 1, adjoint))
+                return fail(DRT3D_EINVAL, "internal: inverse descriptor area too small");
+            TRY(upload_descs(ip.p, ip.area, r.s));
+        }
+    }
+    return DRT3D_OK;
+}
+
 // T = b_l - A x_l in the projection temporary
 static int inv_residual(InvRun& r, int l)
 {
     const long long Nl = r.N >> l;
     float* T = (float*)(r.ws + r.L.tproj);
-    TRY(inv_drt(r, l, inv_x(r, l), T, 0));
+    TRY(run_launches(r.fwd[l].p, r.fwd[l].area, r.s, r.di));
     HIP_TRY(launch_residual(inv_b(r, l), T, T, 12 * Nl * Nl * (3 * Nl - 2), r.s));
     return DRT3D_OK;
 }
@@ -1561,9 +1606,8 @@ static int inv_residual(InvRun& r, int l)
 static int inv_smooth(InvRun& r, int l, float c)
 {
     TRY(inv_residual(r, l));
-    float* V = (float*)(r.ws + r.L.tvol);
-    TRY(inv_drt(r, l, (const float*)(r.ws + r.L.tproj), V, 1));
-    HIP_TRY(launch_hp_filter(V, inv_x(r, l), r.N >> l, c, 1, r.s));
+    TRY(run_launches(r.adj[l].p, r.adj[l].area, r.s, r.di));
+    HIP_TRY(launch_hp_filter((const float*)(r.ws + r.L.tvol), inv_x(r, l), r.N >> l, c, 1, r.s));
     return DRT3D_OK;
 }
 
@@ -1680,6 +1724,7 @@ int drt3d_inverse(const void* proj, void* vol_out, int N, int cycles, const doub
         TRY(inv_lambdas(r));
     }
     HIP_TRY(launch_fill(r.x0, 0.f, (long long)N * N * N, r.s));
+    if (cycles > 0) TRY(inv_prepare(r));
     for (int c = 0; c < cycles; ++c) TRY(inv_vcycle(r, 0));
     return DRT3D_OK;
 }
