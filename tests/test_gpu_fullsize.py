@@ -193,3 +193,90 @@ def test_batched_mixed_float_sampled_against_fp64():
                 worst = max(worst, err / bound)
     print("mixed batch: max |err| / R|f| over the samples = %.3e" % worst)
     assert worst <= FLOAT_TOL
+
+
+def test_djt_adjoint_n128_closed_forms_and_dot_identity():
+    """The DJT adjoint in the benchmark's configuration (N = 128, 12 dodecants,
+    library workspace): J^T 1 = 12 N^2 everywhere; J^T applied to p = e1 gives,
+    per voxel, the sum over the dodecants of N * lambda(z') + N^2 (N-1-x') (the
+    line through (x', y', z') with slopes (s1, s2) sits at e1 = N-1 + l_s1(z') - x',
+    summed over s1 and over the N values of s2); and <J f, p> = <f, J^T p> for a
+    random p, accumulated one dodecant at a time."""
+    import torch
+    from paper_2501_13664_amd._lib import lib
+    api = _api()
+    N = 128
+    E = 2 * N - 1
+    n = N.bit_length() - 1
+    ws = _ws(lib().djt3d_adjoint_workspace_bytes(N, 0xFFF, 0))
+    back = torch.empty((N, N, N), dtype=torch.int32, device="cuda")
+    proj = torch.ones(api.djt3d_out_shape(N), dtype=torch.int32, device="cuda")
+    announce("fullsize djt adjoint N=128 ones")
+    api.djt3d_adjoint(proj, out=back, workspace=ws)
+    assert bool((back == 12 * N * N).all())
+
+    announce("fullsize djt adjoint N=128 e1 ramp")
+    proj.copy_(torch.arange(E, dtype=torch.int32, device="cuda")[:, None].expand(E, E))
+    api.djt3d_adjoint(proj, out=back, workspace=ws)
+    lam = np.array([sum(O.line(n, s, x) for s in range(N)) for x in range(N)], dtype=np.int64)
+    rng = np.random.default_rng(16)
+    vox = _samples(rng, 300, (N, N, N), [(0, 0, 0), (N - 1, N - 1, N - 1), (0, N - 1, 0), (N // 2, 3, N - 2)])
+    mats = []
+    for k in range(12):
+        M = O.frame_matrix(k)
+        o0 = np.array(O.frame_to_orig(k, N, (0, 0, 0)), dtype=np.int64)
+        mats.append((M, -M @ o0))
+    ref = []
+    for (x, y, z) in vox:
+        acc = 0
+        for M, off in mats:
+            xp, yp, zp = M @ np.array([x, y, z], dtype=np.int64) + off
+            acc += N * int(lam[zp]) + N * N * (N - 1 - int(xp))
+        ref.append(acc)
+    idx = torch.tensor(vox, dtype=torch.long, device="cuda")
+    got = back[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    assert np.array_equal(got, O.wrap_int32(np.array(ref, dtype=np.int64)))
+
+    announce("fullsize djt adjoint N=128 dot identity")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(17)
+    proj = torch.randint(-8, 8, api.djt3d_out_shape(N), generator=g, dtype=torch.int32, device="cuda")
+    f = torch.randint(-8, 8, (N, N, N), generator=g, dtype=torch.int32, device="cuda")
+    api.djt3d_adjoint(proj, out=back, workspace=ws)
+    del ws
+    Jf = api.djt3d_forward(f)
+    lhs = sum(int((Jf[k].to(torch.int64) * proj[k]).sum()) for k in range(12))
+    rhs = int((f.to(torch.int64) * back).sum())
+    assert lhs == rhs
+    del proj, Jf
+    torch.cuda.empty_cache()
+
+
+def test_inverse_n128_converges_and_is_linear():
+    """The inverse in the benchmark's configuration (N = 128, 12 dodecants):
+    on the corners-and-centre cube the error falls every cycle and is below
+    2e-3 after ten; and inverse(A f + 2 A g) = inverse(A f) + 2 inverse(A g)
+    within float32 rounding (the scheme is linear in its data)."""
+    import torch
+    api = _api()
+    N = 128
+    f = torch.from_numpy(workloads.corners_and_centre(N).astype(np.float32)).cuda()
+    announce("fullsize inverse N=128 eigenvalues")
+    lams = api.drt3d_inverse_lambdas(N)
+    b = api.drt3d_forward(f)
+    errs = []
+    for cycles in (1, 3, 6, 10):
+        announce("fullsize inverse N=128 cycles=%d" % cycles)
+        x = api.drt3d_inverse(b, cycles, lams=lams)
+        errs.append(float(torch.linalg.vector_norm(x - f) / torch.linalg.vector_norm(f)))
+    print("N=128 errors after 1, 3, 6, 10 cycles:", errs)
+    assert all(b2 < a for a, b2 in zip(errs, errs[1:])) and errs[-1] < 2e-3
+    announce("fullsize inverse N=128 linearity")
+    gv = torch.from_numpy(workloads.normal_cube(N, seed=18)).cuda()
+    bg = api.drt3d_forward(gv)
+    xs = api.drt3d_inverse(b + 2 * bg, 3, lams=lams)
+    xf = api.drt3d_inverse(b, 3, lams=lams)
+    xg = api.drt3d_inverse(bg, 3, lams=lams)
+    rel = float(torch.linalg.vector_norm(xs - xf - 2 * xg) / torch.linalg.vector_norm(xs))
+    print("linearity: %.2e" % rel)
+    assert rel < 1e-5
