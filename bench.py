@@ -22,7 +22,8 @@ per-volume calls; the differentiable transform (forward + backward through
 autograd) of a batch of 8 float32 N=128 cubes against per-volume forward +
 adjoint calls (both check that the two ways give bit-identical results); the
 3D DJT of one N=128 int32 cube, with U = 12 * 8 N^3 (N-1) voxel-stage updates,
-and its adjoint; and the iterative inverse of a float32 N=128 DRT (ten
+and its adjoint; Algorithm 2's merged net of the projections (with the
+adjoint); and the iterative inverse of a float32 N=128 DRT (ten
 V-cycles) with its error after each cycle count.
 
 --copy-calibration runs only a plain 1 GiB device-to-device copy (five times),
@@ -235,6 +236,18 @@ def djt_rate(api, torch, reps=3):
     return res
 
 
+def merge_net_rate(api, torch, proj, reps=3):
+    """Algorithm 2's merged net of the benchmark's N=512 projections: reads the
+    12 dodecants once, writes the 4N x 4N x (3N-2) net once (corners zeroed)."""
+    N = int(proj.shape[1])
+    net = torch.empty((4 * N, 4 * N, 3 * N - 2), dtype=proj.dtype, device="cuda")
+    ms = _best_ms(torch, lambda: api.drt3d_merge_net(proj, out=net), reps)
+    nbytes = 4.0 * (12 + 16) * N * N * (3 * N - 2)
+    del net
+    return {"workload": "drt3d_merge_net N=%d int32 (the forward's projections)" % N, "ms": ms,
+            "bytes": nbytes, "GBps": nbytes / (ms / 1e3) / 1e9, "frac_of_hbm_peak": nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+
 def inverse_rate(api, torch, N=128, cycles=10, reps=2):
     """The iterative inverse (Sec. 5.2) of the 12-dodecant float32 DRT of the
     corners-and-centre cube (value 1 on the 8 corners and the centre voxel) at
@@ -366,6 +379,7 @@ def main():
     }
     if not args.no_adjoint:
         line["adjoint"] = adjoint_rate(api, torch, out, N)
+        line["merge_net"] = merge_net_rate(api, torch, out)
     del ws
     torch.cuda.empty_cache()
     if not args.no_batched:

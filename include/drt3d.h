@@ -138,6 +138,19 @@ int djt3d_adjoint_batched(int count, const void* const* projs, void* const* vols
                           const int* Ns, uint32_t mask, int dtype,
                           void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- merged output (Algorithm 2) ---------------------------------------------- */
+/* Elements of the merged net: 16 * N * N * (3N-2); 0 if N is invalid. */
+size_t drt3d_net_elems(int N);
+/* Algorithm 2's global output (Sec. 3.2): each of the 12 dodecants' outputs
+ * (proj: the drt3d_forward layout for DRT3D_ALL) is rotated by its OutOrder row
+ * (axes (s1, s2) permuted by |OutOrder|, then each axis with a negative entry
+ * flipped; dd is never moved) and placed at block DodecantCoords(k) of the
+ * net [4N][4N][3N-2]: net[bi*N + i][bj*N + j][dd]. The four corner blocks, which
+ * no dodecant fills, are written as zeros; net is fully overwritten. A layout
+ * transform on the GPU (one read of proj, one write of net); the net is not
+ * claimed to be continuous across block edges. */
+int drt3d_merge_net(const void* proj, void* net, int N, int dtype, void* stream);
+
 /* ---- inverse ---------------------------------------------------------------- */
 /* Iterative inverse of the 12-dodecant DRT (Sec. 5.2), float32 only: given
  * proj = drt3d_forward(f) for all 12 dodecants ([12][N][N][3N-2] float32),

@@ -41,6 +41,8 @@ SIGNATURES = {
     "djt3d_forward_batched": (_int, [_int, _ptrs, _ptrs, _ints, _u32, _int, _vp, _sz, _vp]),
     "drt3d_adjoint_batched": (_int, [_int, _ptrs, _ptrs, _ints, _u32, _int, _vp, _sz, _vp]),
     "djt3d_adjoint_batched": (_int, [_int, _ptrs, _ptrs, _ints, _u32, _int, _vp, _sz, _vp]),
+    "drt3d_net_elems": (_sz, [_int]),
+    "drt3d_merge_net": (_int, [_vp, _vp, _int, _int, _vp]),
     "drt3d_inverse_workspace_bytes": (_sz, [_int]),
     "drt3d_inverse": (_int, [_vp, _vp, _int, _int, ctypes.POINTER(ctypes.c_double), _vp, _sz, _vp]),
     "drt3d_inverse_lambdas": (_int, [_int, ctypes.POINTER(ctypes.c_double), _vp, _sz, _vp]),

@@ -16,7 +16,7 @@ from ._lib import DRT3D_ALL, DRT3D_F32, DRT3D_I32, check, lib
 __all__ = [
     "DRT3D_ALL", "drt3d_forward", "djt3d_forward", "drt3d_adjoint", "djt3d_adjoint",
     "drt3d_forward_batched", "djt3d_forward_batched", "drt3d_adjoint_batched", "djt3d_adjoint_batched",
-    "drt3d_inverse", "drt3d_inverse_lambdas",
+    "drt3d_inverse", "drt3d_inverse_lambdas", "drt3d_merge_net",
     "drt3d_out_shape", "djt3d_out_shape", "drt3d_autotune", "drt3d_tuning_string",
     "drt3d_set_tuning", "profile", "dodecant_count",
 ]
@@ -222,6 +222,24 @@ def djt3d_adjoint_batched(projs: Sequence[torch.Tensor], mask: int = DRT3D_ALL,
     _batched("djt3d_adjoint_batched", "djt3d_adjoint_batched_workspace_bytes", projs, outs, Ns, mask, dt,
              projs[0].device, workspace, stream)
     return list(outs)
+
+
+def drt3d_merge_net(proj: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Algorithm 2's merged output: the 12-dodecant DRT rotated and placed in a
+    [4N][4N][3N-2] net (the four corner blocks zero)."""
+    if proj.dim() != 4:
+        raise ValueError("proj must be [12][N][N][3N-2]")
+    N = int(proj.shape[1])
+    if tuple(proj.shape) != drt3d_out_shape(N) or not proj.is_cuda or not proj.is_contiguous():
+        raise ValueError("proj must be a contiguous 12-dodecant device tensor of shape %s" % (drt3d_out_shape(N),))
+    dt = _dtype_code(proj)
+    shape = (4 * N, 4 * N, 3 * N - 2)
+    if out is None:
+        out = torch.empty(shape, dtype=proj.dtype, device=proj.device)
+    elif tuple(out.shape) != shape or out.dtype != proj.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous %s tensor of shape %s" % (proj.dtype, shape))
+    check(lib().drt3d_merge_net(_ptr(proj), _ptr(out), N, dt, _stream(stream)))
+    return out
 
 
 def _inverse_workspace(N: int, device, workspace):

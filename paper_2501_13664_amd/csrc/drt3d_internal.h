@@ -134,5 +134,7 @@ hipError_t launch_power_start(float* v, int N, hipStream_t s);
 size_t norm_scratch_bytes();
 // scratch[norm_scratch_bytes()]: ends holding |w| (a double) at its last slot
 hipError_t launch_normalize(const float* w, float* v, long long n, double* scratch, hipStream_t s);
+// Algorithm 2's merged 4N x 4N x (3N-2) net from the 12-dodecant output.
+hipError_t launch_merge_net(int is_float, const void* R, void* net, int N, hipStream_t s);
 
 }  // namespace drt3d

@@ -1465,6 +1465,22 @@ int djt3d_adjoint_batched(int count, const void* const* projs, void* const* vols
     return batched(S_DJT, 1, count, projs, vols_out, Ns, mask, dtype, workspace, workspace_bytes, stream);
 }
 
+// ------------------------------------------------------------------ merged net ABI
+size_t drt3d_net_elems(int N)
+{
+    if (ilog2_exact(N) < 1 || N > DRT3D_MAX_N) return 0;
+    return (size_t)16 * N * N * (3 * (size_t)N - 2);
+}
+
+int drt3d_merge_net(const void* proj, void* net, int N, int dtype, void* stream)
+{
+    TRY(check_common(N, DRT3D_ALL, dtype));
+    TRY(check_ptr(proj, "proj"));
+    TRY(check_ptr(net, "net"));
+    HIP_TRY(launch_merge_net(dtype == DRT3D_F32, proj, net, N, (hipStream_t)stream));
+    return DRT3D_OK;
+}
+
 // ------------------------------------------------------------------ inverse ABI
 // Iterative inverse of the 12-dodecant DRT (Sec. 5.2): Press's iterative
 // improvement with the approximate inverse H A^T (H the printed 3x3x3
