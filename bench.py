@@ -22,8 +22,9 @@ per-volume calls; the differentiable transform (forward + backward through
 autograd) of a batch of 8 float32 N=128 cubes against per-volume forward +
 adjoint calls (both check that the two ways give bit-identical results); the
 3D DJT of one N=128 int32 cube, with U = 12 * 8 N^3 (N-1) voxel-stage updates,
-and its adjoint; Algorithm 2's merged net of the projections (with the
-adjoint); and the iterative inverse of a float32 N=128 DRT (ten
+and its adjoint; Algorithm 2's merged net of the projections and the same cube's
+forward as uint8 with narrow storage (both with the adjoint); and the
+iterative inverse of a float32 N=128 DRT (ten
 V-cycles) with its error after each cycle count.
 
 --copy-calibration runs only a plain 1 GiB device-to-device copy (five times),
@@ -236,6 +237,25 @@ def djt_rate(api, torch, reps=3):
     return res
 
 
+def narrow_rate(api, torch, vol_np, ref, reps=5):
+    """The same N=512 cube as uint8 (its values are 0, 1 and 16) through the
+    narrow-storage forward: the identical int32 projections with fewer HBM
+    bytes (1-byte volume copies, 16-bit first-stage partial sums)."""
+    N = vol_np.shape[0]
+    v8 = torch.from_numpy(vol_np.astype("uint8")).cuda()
+    out = torch.empty_like(ref)
+    from paper_2501_13664_amd._lib import lib
+    ws = torch.empty(lib().drt3d_workspace_bytes(N, 0xFFF, 2), dtype=torch.uint8, device="cuda")
+    with api.profile() as prof:
+        ms = _best_ms(torch, lambda: api.drt3d_forward(v8, out=out, workspace=ws), reps)
+    same = bool(torch.equal(out, ref))
+    recs = prof.records
+    U = updates(N)
+    return {"workload": "drt3d_forward N=%d, the benchmark cube as uint8, int32 out, 12 dodecants" % N,
+            "ms": ms, "updates_per_s": U / (ms / 1e3), "bit_identical_to_int32": same,
+            "kernels": {k: {"ms_per_launch": v[0] / v[1], "alg_GBps": v[2] / (v[0] / 1e3) / 1e9} for k, v in recs.items()}}
+
+
 def merge_net_rate(api, torch, proj, reps=3):
     """Algorithm 2's merged net of the benchmark's N=512 projections: reads the
     12 dodecants once, writes the 4N x 4N x (3N-2) net once (corners zeroed)."""
@@ -380,6 +400,7 @@ def main():
     if not args.no_adjoint:
         line["adjoint"] = adjoint_rate(api, torch, out, N)
         line["merge_net"] = merge_net_rate(api, torch, out)
+        line["narrow_u8"] = narrow_rate(api, torch, vol_np, out)
     del ws
     torch.cuda.empty_cache()
     if not args.no_batched:

@@ -57,7 +57,9 @@ extern "C" {
 
 typedef enum {
     DRT3D_I32 = 0, /* int32 in, int32 out, wrap-around arithmetic */
-    DRT3D_F32 = 1  /* float32 in, float32 out */
+    DRT3D_F32 = 1, /* float32 in, float32 out */
+    DRT3D_U8 = 2   /* uint8 volume in, int32 out (drt3d_forward only, N >= 32): the
+                      int32 transform of the same values, bit for bit */
 } drt3d_dtype;
 
 typedef enum {
@@ -92,7 +94,13 @@ size_t djt3d_adjoint_batched_workspace_bytes(int count, const int* Ns, uint32_t 
 /* ---- transforms ----------------------------------------------------------- */
 /* 3D DRT of planes, Algorithm 1 (stage map eq. (11)) over the dodecants of
  * `mask` (Algorithm 2's input frames). vol: [N][N][N] of dtype; out:
- * drt3d_out_elems(N, mask) elements of dtype, fully overwritten. */
+ * drt3d_out_elems(N, mask) elements of dtype (int32 for DRT3D_U8), fully
+ * overwritten. DRT3D_U8 keeps the data narrow in HBM where it fits (Sec. 6
+ * points at 8-bit data): the volume and its frame copies at 1 byte, the first
+ * pass's partial sums (at most 2^6 voxels of 0..255) at 2 bytes, the rest at 4,
+ * with 32-bit arithmetic throughout; it needs a tuning whose passes all have
+ * shape-specialised kernels (the built-in ones for N = 32..512), else
+ * DRT3D_EUNSUPPORTED. */
 int drt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype,
                   void* workspace, size_t workspace_bytes, void* stream);
 

@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_HERE, "libdrt3d.so")
 
 DRT3D_I32 = 0
 DRT3D_F32 = 1
+DRT3D_U8 = 2
 DRT3D_ALL = 0xFFF
 STATUS = {0: "DRT3D_OK", -1: "DRT3D_EINVAL", -2: "DRT3D_ENOMEM", -3: "DRT3D_EHIP", -4: "DRT3D_EUNSUPPORTED"}
 

@@ -11,7 +11,7 @@ from typing import List, Optional, Sequence
 
 import torch
 
-from ._lib import DRT3D_ALL, DRT3D_F32, DRT3D_I32, check, lib
+from ._lib import DRT3D_ALL, DRT3D_F32, DRT3D_I32, DRT3D_U8, check, lib
 
 __all__ = [
     "DRT3D_ALL", "drt3d_forward", "djt3d_forward", "drt3d_adjoint", "djt3d_adjoint",
@@ -71,14 +71,20 @@ def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
 
 def drt3d_forward(vol: torch.Tensor, mask: int = DRT3D_ALL, out: Optional[torch.Tensor] = None,
                   workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """3D DRT of planes over the dodecants of `mask`: [popcount][N][N][3N-2]."""
+    """3D DRT of planes over the dodecants of `mask`: [popcount][N][N][3N-2].
+
+    A uint8 volume gives the int32 result of the same values, computed with
+    narrow storage in HBM (N >= 32)."""
     N = _cube(vol)
-    dt = _dtype_code(vol)
+    if vol.dtype == torch.uint8:
+        dt, odt = DRT3D_U8, torch.int32
+    else:
+        dt, odt = _dtype_code(vol), vol.dtype
     shape = drt3d_out_shape(N, mask)
     if out is None:
-        out = torch.empty(shape, dtype=vol.dtype, device=vol.device)
-    elif tuple(out.shape) != shape or out.dtype != vol.dtype or not out.is_contiguous():
-        raise ValueError("out must be a contiguous %s tensor of shape %s" % (vol.dtype, shape))
+        out = torch.empty(shape, dtype=odt, device=vol.device)
+    elif tuple(out.shape) != shape or out.dtype != odt or not out.is_contiguous():
+        raise ValueError("out must be a contiguous %s tensor of shape %s" % (odt, shape))
     need = lib().drt3d_workspace_bytes(N, mask, dt)
     ws = _workspace(need, vol.device, workspace)
     check(lib().drt3d_forward(_ptr(vol), _ptr(out), N, mask, dt, _ptr(ws), ws.numel() * ws.element_size(),

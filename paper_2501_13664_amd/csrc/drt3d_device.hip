@@ -7,9 +7,17 @@ namespace drt3d {
 
 // ---------------------------------------------------------------------------
 // Shape-specialised kernels live in their own translation units.
-static const void* fast_kernel(int is_float, int kx, int ky, int nch, int mode, int waves)
+static const void* fast_kernel(int is_float, int kx, int ky, int nch, int mode, int waves, int sb = 4, int db = 4)
 {
     if (nch < 1 || nch > 6) return nullptr;
+    if (sb != 4 || db != 4) {
+        if (is_float || waves != 8) return nullptr;
+        if (kx == 3 && ky == 3) return drt_fast_kernel_narrow_3_3(nch, mode, sb, db);
+        if (kx == 2 && ky == 2) return drt_fast_kernel_narrow_2_2(nch, mode, sb, db);
+        if (kx == 3 && ky == 2) return drt_fast_kernel_narrow_3_2(nch, mode, sb, db);
+        if (kx == 2 && ky == 3) return drt_fast_kernel_narrow_2_3(nch, mode, sb, db);
+        return nullptr;
+    }
     if (kx == 3 && ky == 3) return drt_fast_kernel_3_3(is_float, nch, mode, waves);
     if (kx == 2 && ky == 2) return drt_fast_kernel_2_2(is_float, nch, mode, waves);
     if (kx == 3 && ky == 2) return drt_fast_kernel_3_2(is_float, nch, mode, waves);
@@ -36,6 +44,16 @@ hipError_t set_drt_lds_limit(int is_float, size_t bytes)
                     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
                     if (e != hipSuccess) return e;
                 }
+    const int narrow[4][3] = {{0, 1, 2}, {0, 2, 4}, {1, 2, 4}, {1, 1, 4}};  // (mode, sb, db)
+    if (!is_float)
+        for (auto& sh : shapes)
+            for (int nc = 1; nc <= 6; ++nc)
+                for (auto& m : narrow) {
+                    const void* k = fast_kernel(0, sh[0], sh[1], nc, m[0], 8, m[1], m[2]);
+                    if (!k) continue;
+                    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+                    if (e != hipSuccess) return e;
+                }
     if (is_float)
         return hipFuncSetAttribute(reinterpret_cast<const void*>(&drt_pass_kernel<float>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -43,15 +61,15 @@ hipError_t set_drt_lds_limit(int is_float, size_t bytes)
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-int drt_fast_available(int kx, int ky, int nch, int waves)
+int drt_fast_available(int kx, int ky, int nch, int waves, int mode, int sb, int db)
 {
-    return fast_kernel(0, kx, ky, nch, 0, waves) != nullptr;
+    return fast_kernel(0, kx, ky, nch, mode, waves, sb, db) != nullptr;
 }
 
 hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int mode, int waves, const DrtDesc* d_descs,
-                           int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s)
+                           int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s, int sb, int db)
 {
-    const void* k = fast_kernel(is_float, kx, ky, nch, mode, waves);
+    const void* k = fast_kernel(is_float, kx, ky, nch, mode, waves, sb, db);
     if (!k) return hipErrorInvalidValue;
     void* args[] = {&d_descs, &ndesc, &total_wg};
     return hipLaunchKernel(k, dim3(grid), dim3(64 * waves), args, lds_bytes, s);
@@ -76,6 +94,14 @@ hipError_t launch_djt_pass(int is_float, int K, int ncc, int nco, const DjtDesc*
     if (!k) return hipErrorInvalidValue;
     void* args[] = {&d_descs, &ndesc, &total_wg};
     return hipLaunchKernel(k, dim3(grid), dim3(512), args, lds_bytes, s);
+}
+
+hipError_t launch_transpose_u8(const TransDesc* d_descs, int ndesc, long long total_wg, hipStream_t s)
+{
+    if (total_wg <= 0) return hipSuccess;
+    if (total_wg > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(transpose_kernel<uint8_t>, dim3((unsigned)total_wg), dim3(256), 0, s, d_descs, ndesc);
+    return hipGetLastError();
 }
 
 hipError_t launch_transpose(int is_float, const TransDesc* d_descs, int ndesc, long long total_wg,

@@ -37,6 +37,28 @@ static const void* shape_kernel(int nch, int mode)
     }
 }
 
+// Narrow storage (uint32 arithmetic, eight wavefronts): source and destination
+// bytes per element (sb, db) in {(1, 2), (2, 4), (1, 4)}, forward modes only.
+template <int MODE, int SB, int DB>
+static const void* narrow_kernel(int nch)
+{
+#define DRT3D_NC(NC)                                                                                        \
+    if (nch == NC)                                                                                          \
+        return reinterpret_cast<const void*>(&fast::drt_pass_fast<uint32_t, DRT3D_KX, DRT3D_KY, NC, MODE, 8, SB, DB>);
+    DRT3D_NC(1) DRT3D_NC(2) DRT3D_NC(3) DRT3D_NC(4) DRT3D_NC(5) DRT3D_NC(6)
+#undef DRT3D_NC
+    return nullptr;
+}
+
+const void* DRT3D_CAT(drt_fast_kernel_narrow_, DRT3D_KX, DRT3D_KY)(int nch, int mode, int sb, int db)
+{
+    if (sb == 1 && db == 2 && mode == 0) return narrow_kernel<0, 1, 2>(nch);
+    if (sb == 2 && db == 4 && mode == 0) return narrow_kernel<0, 2, 4>(nch);
+    if (sb == 2 && db == 4 && mode == 1) return narrow_kernel<1, 2, 4>(nch);
+    if (sb == 1 && db == 4 && mode == 1) return narrow_kernel<1, 1, 4>(nch);
+    return nullptr;
+}
+
 // mode: 0 forward into a stage buffer, 1 the forward's last pass, 2 adjoint;
 // waves: 8, or 16 for the 3.3 shape
 const void* DRT3D_CAT(drt_fast_kernel_, DRT3D_KX, DRT3D_KY)(int is_float, int nch, int mode, int waves)

@@ -44,6 +44,7 @@ struct DrtDesc {
     // same original column block in work groups 8 apart (same XCD, close in
     // time), sharing its loads through that XCD's L2
     int xcd_run;
+    int sb, db;            // bytes per element of the source and destination in HBM (4, or narrow storage)
     int phys[kMaxSlots];   // slot -> slot index inside the source (stage buffer or projections)
     int dphys[kMaxSlots];  // slot -> slot index inside the destination (dst_mode 0)
     int accum[kMaxSlots];  // dst_mode 1: add into the volume (1) or overwrite (0)
@@ -111,6 +112,11 @@ const void* drt_fast_kernel_3_3(int is_float, int nch, int mode, int waves);
 const void* drt_fast_kernel_2_2(int is_float, int nch, int mode, int waves);
 const void* drt_fast_kernel_3_2(int is_float, int nch, int mode, int waves);
 const void* drt_fast_kernel_2_3(int is_float, int nch, int mode, int waves);
+// the same passes over narrow storage (see drt_pass_fast's SB, DB)
+const void* drt_fast_kernel_narrow_3_3(int nch, int mode, int sb, int db);
+const void* drt_fast_kernel_narrow_2_2(int nch, int mode, int sb, int db);
+const void* drt_fast_kernel_narrow_3_2(int nch, int mode, int sb, int db);
+const void* drt_fast_kernel_narrow_2_3(int nch, int mode, int sb, int db);
 const void* djt_pass_kernel_ptr(int is_float, int K, int ncc, int nco);
 const void* djt_adj_kernel_ptr(int is_float, int K, int ncc);
 hipError_t launch_djt_adj(int is_float, int K, int ncc, const DjtDesc* d_descs, int ndesc, long long total_wg,
@@ -118,9 +124,13 @@ hipError_t launch_djt_adj(int is_float, int K, int ncc, const DjtDesc* d_descs, 
 // Shape-specialised DRT pass kernels (eight wavefronts per work group).
 // mode: 0 forward into a stage buffer, 1 the forward's last pass (every
 // descriptor writes the caller's output), 2 adjoint.
-int drt_fast_available(int kx, int ky, int nch, int waves);
+// sb, db: bytes per element of the pass's source and destination (4 unless
+// the call is over narrow storage).
+int drt_fast_available(int kx, int ky, int nch, int waves, int mode = 0, int sb = 4, int db = 4);
 hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int mode, int waves, const DrtDesc* d_descs,
-                           int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
+                           int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s, int sb = 4,
+                           int db = 4);
+hipError_t launch_transpose_u8(const TransDesc* d_descs, int ndesc, long long total_wg, hipStream_t s);
 
 // Iterative inverse (float32): filter, residual, restriction, prolongation,
 // and the vector steps of the power iteration.

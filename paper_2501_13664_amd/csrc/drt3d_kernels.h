@@ -93,6 +93,30 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int off, uint32
     __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
 }
 
+// Narrow storage (1- or 2-byte elements in HBM, 32-bit arithmetic in
+// registers and LDS): loads zero-extend, stores keep the low bytes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc_bytes(const void* base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kBufferConfig);
+}
+
+template <int B>
+__device__ __forceinline__ uint32_t bload_n(__amdgpu_buffer_rsrc_t r, int off)
+{
+    static_assert(B == 1 || B == 2 || B == 4, "element bytes");
+    if constexpr (B == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+    else if constexpr (B == 2) return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+    else return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
+
+template <int B>
+__device__ __forceinline__ void bstore_n(__amdgpu_buffer_rsrc_t r, int off, uint32_t v)
+{
+    static_assert(B == 2 || B == 4, "element bytes");
+    if constexpr (B == 4) __builtin_amdgcn_raw_buffer_store_b32(v, r, off, 0, 0);
+    else __builtin_amdgcn_raw_buffer_store_b16((unsigned short)v, r, off, 0, 0);
+}
+
 template <typename T> __device__ __forceinline__ uint32_t to_bits(T v) { return __builtin_bit_cast(uint32_t, v); }
 template <typename T> __device__ __forceinline__ T from_bits(uint32_t v) { return __builtin_bit_cast(T, v); }
 
@@ -599,10 +623,16 @@ __device__ __forceinline__ int py_of(int wave, int i) { return (wave >> KX) + i 
 // (FINAL), 2 an adjoint pass; fixing it at compile time drops the other
 // modes' bookkeeping from the kernel.
 // NW: wavefronts per work group (8, or 16 for the 64-column 3.3 passes).
-template <typename T, int KX, int KY, int NCH, int MODE, int NW>
+// SB, DB: bytes per element of the source and destination in HBM (4, or the
+// narrow storage of 8-bit volumes: 1 for the volume, 2 for the first stage
+// buffer, whose partial sums of at most 2^(KX+KY) <= 256 voxels of 0..255 fit
+// 16 bits). Arithmetic stays 32-bit.
+template <typename T, int KX, int KY, int NCH, int MODE, int NW, int SB = 4, int DB = 4>
 __global__ void __launch_bounds__(64 * NW, NW == 16 ? 8 : 6)
 drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 {
+    static_assert((SB == 4 && DB == 4) || (MODE != 2 && sizeof(T) == 4), "narrow storage: forward passes only");
+    constexpr int LINE = 128 / DB;  // destination elements per 128-byte line
     constexpr bool FINAL = MODE == 1;
     constexpr int adjoint = MODE == 2 ? 1 : 0;
     constexpr int NS = 1 << (KX + KY), SPW = NS / NW, L = 64 * NCH;
@@ -663,23 +693,23 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
         __amdgpu_buffer_rsrc_t rs_src, rs_dst;
         int so, sys, ssd, sE, do_, dys, dsd, dE;
         if (d->src_mode == 0) {
-            const T* base = reinterpret_cast<const T*>(d->src) + d->phys[slot] * d->src_slot_stride;
-            rs_src = make_rsrc(base, (int)d->src_slot_stride);
+            const char* base = reinterpret_cast<const char*>(d->src) + (long long)SB * d->phys[slot] * d->src_slot_stride;
+            rs_src = make_rsrc_bytes(base, SB * (int)d->src_slot_stride);
             const int c1 = adjoint ? c1s : c1b, c2 = adjoint ? c2s : c2b;
             so = ((c1 << n) + c2) * d->P_in;
             sys = adjoint ? d->P_in : (d->P_in << my0);
             ssd = 1;
             sE = d->E_in;
         } else {
-            rs_src = make_rsrc(reinterpret_cast<const T*>(d->vsrc[fm.group]), N * N * N);
+            rs_src = make_rsrc_bytes(d->vsrc[fm.group], SB * N * N * N);
             so = fm.base + fm.sx * c1b + fm.sy * c2b;
             sys = fm.sy * (1 << my0);
             ssd = fm.sd;
             sE = N;
         }
         if (d->dst_mode == 0) {
-            T* base = reinterpret_cast<T*>(d->dst) + d->dphys[slot] * d->dst_slot_stride;
-            rs_dst = make_rsrc(base, (int)d->dst_slot_stride);
+            char* base = reinterpret_cast<char*>(d->dst) + (long long)DB * d->dphys[slot] * d->dst_slot_stride;
+            rs_dst = make_rsrc_bytes(base, DB * (int)d->dst_slot_stride);
             const int c1 = adjoint ? c1b : c1s, c2 = adjoint ? c2b : c2s;
             do_ = ((c1 << n) + c2) * d->P_out;
             dys = adjoint ? (d->P_out << my0) : d->P_out;
@@ -714,13 +744,13 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
                 const int dd0 = adjoint ? d0 : d0 - H - sx0 * px - sy0 * py;
                 const int colo = so + y * sys;
                 const int dl = dd0 + lane;
-                const int ob = 4 * colo + (ssd > 0 ? 4 * dl : -4 * dl);
+                const int ob = SB * colo + (ssd > 0 ? SB * dl : -SB * dl);
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
                     // lanes outside the column get an offset past the resource:
                     // the hardware returns 0 for them without touching memory
                     const bool in = (unsigned)(dl + 64 * c) < (unsigned)sE;
-                    v[i][c] = bload(rs_src, in ? ob + (ssd > 0 ? 256 * c : -256 * c) : -1);
+                    v[i][c] = bload_n<SB>(rs_src, in ? ob + (ssd > 0 ? 64 * SB * c : -64 * SB * c) : -1);
                 }
             }
         };
@@ -749,23 +779,25 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
                 const int y = adjoint ? py : bitrev(py, KY);
                 const int dd0 = adjoint ? d0 - sx0 * px - sy0 * py : d0;
                 const int colo = do_ + y * dys;
-                const int mis = dsd > 0 ? (colo & 31) : ((colo + 1) & 31);
-                auto line_floor = [&](int x) { return dsd > 0 ? x - ((mis + x) & 31) : x - ((x - mis) & 31); };
+                const int mis = dsd > 0 ? (colo & (LINE - 1)) : ((colo + 1) & (LINE - 1));
+                auto line_floor = [&](int x) {
+                    return dsd > 0 ? x - ((mis + x) & (LINE - 1)) : x - ((x - mis) & (LINE - 1));
+                };
                 const int fbeg = dd0 <= 0 ? dd0 : line_floor(dd0);
                 const int fend = last_tile ? dd0 + T_ : line_floor(dd0 + T_);
                 const T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + q0 - dd0;
                 const int cnt = fend - fbeg;
                 const int fl = fbeg + lane;
-                const int ob = 4 * colo + (dsd > 0 ? 4 * fl : -4 * fl);
+                const int ob = DB * colo + (dsd > 0 ? DB * fl : -DB * fl);
 #pragma unroll
                 for (int c = 0; c < NCH + 1; ++c) {
                     const int k = 64 * c + lane;
                     const int dd = fbeg + k;
                     if (k < cnt && (unsigned)dd < (unsigned)dE) {
                         T val = dd < dd0 ? from_bits<T>(carry[i]) : live ? sl[dd] : zero_of<T>();
-                        const int off = ob + (dsd > 0 ? 256 * c : -256 * c);
+                        const int off = ob + (dsd > 0 ? 64 * DB * c : -64 * DB * c);
                         if (accum) val += from_bits<T>(bload(rs_dst, off));
-                        bstore(rs_dst, off, to_bits(val));
+                        bstore_n<DB>(rs_dst, off, to_bits(val));
                     }
                 }
                 if (!last_tile) {

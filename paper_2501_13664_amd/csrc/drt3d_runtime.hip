@@ -393,6 +393,7 @@ struct Step {
     const void* t_in = nullptr;
     void* t_out = nullptr;
     int t_R = 0, t_C = 0, t_batches = 0, t_add = 0;
+    int t_bytes = 4;  // transpose element bytes (1: an 8-bit volume)
     // sum: t_out[i] = (t_add ? t_out[i] : 0) + sum over p < t_R of t_in[p * sum_n + i]
     long long sum_n = 0;
 };
@@ -402,6 +403,8 @@ struct Launch {
     std::string name;
     int fast_kx = -1, fast_ky = -1, fast_nch = -1;  // shape-specialised DRT kernel, if any
     int fast_mode = 0;                              // ... 0 forward, 1 forward last pass, 2 adjoint
+    int fast_sb = 4, fast_db = 4;                   // ... storage bytes of its source and destination
+    int tr_bytes = 4;                               // transposes: element bytes
     int djt_k = 0, djt_ncc = 0, djt_nco = 0;        // DJT: stages fused per pass, LDS/output row chunks
     int djt_adj = 0;                                // DJT: the pass's transpose
     const void* sum_in = nullptr;                   // S_SUM
@@ -484,6 +487,7 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
         }
         if (s0->kind == S_TRANSPOSE) {
             // steps of one key write different volumes: one launch is race-free
+            L.tr_bytes = s0->t_bytes;
             L.first = (int)prog.tr.size();
             long long wg = 0;
             for (size_t q = i; q < j; ++q) {
@@ -547,14 +551,19 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
                 const DrtDesc& e = prog.drt[q];
                 // the specialised kernel addresses each region with 32-bit
                 // byte offsets: N <= 512 keeps every region below 2^31 bytes
-                same = same && e.Kx == f.Kx && e.Ky == f.Ky && e.L == f.L && e.N <= 512 && e.adjoint == f.adjoint;
+                same = same && e.Kx == f.Kx && e.Ky == f.Ky && e.L == f.L && e.N <= 512 && e.adjoint == f.adjoint &&
+                       e.sb == f.sb && e.db == f.db;
                 final_pass = final_pass && !e.adjoint && e.dst_mode == 0 && e.nt_store;
             }
-            if (same && (f.L & 63) == 0 && drt_fast_available(f.Kx, f.Ky, f.L >> 6, L.block / 64)) {
+            const int mode = f.adjoint ? 2 : final_pass ? 1 : 0;
+            const int fsb = f.sb ? f.sb : 4, fdb = f.db ? f.db : 4;
+            if (same && (f.L & 63) == 0 && drt_fast_available(f.Kx, f.Ky, f.L >> 6, L.block / 64, mode, fsb, fdb)) {
                 L.fast_kx = f.Kx;
                 L.fast_ky = f.Ky;
                 L.fast_nch = f.L >> 6;
-                L.fast_mode = f.adjoint ? 2 : final_pass ? 1 : 0;
+                L.fast_mode = mode;
+                L.fast_sb = fsb;
+                L.fast_db = fdb;
             }
         }
         prog.launches.push_back(L);
@@ -630,7 +639,7 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
                             di.max_lds);
             if (L.fast_kx >= 0)
                 e = launch_drt_fast(p.is_float, L.fast_kx, L.fast_ky, L.fast_nch, L.fast_mode, L.block / 64, d_drt + L.first, L.ndesc,
-                                    L.total_wg, grid_for(L.total_wg, di, L.persistent), L.lds, s);
+                                    L.total_wg, grid_for(L.total_wg, di, L.persistent), L.lds, s, L.fast_sb, L.fast_db);
             else
                 e = launch_drt_pass(p.is_float, d_drt + L.first, L.ndesc, L.total_wg, L.block,
                                     grid_for(L.total_wg, di, L.persistent), L.lds, s);
@@ -646,6 +655,8 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
                                     grid_for(L.total_wg, di, L.persistent), L.lds, s);
         } else if (L.kind == S_SUM) {
             e = launch_sum_parts(p.is_float, L.sum_in, L.sum_parts, L.sum_out, L.sum_n, L.sum_accum, s);
+        } else if (L.tr_bytes == 1) {
+            e = launch_transpose_u8(d_tr + L.first, L.ndesc, L.total_wg, s);
         } else {
             e = launch_transpose(p.is_float, d_tr + L.first, L.ndesc, L.total_wg, s);
         }
@@ -774,8 +785,10 @@ static size_t drt_ws_volume_bytes(int N, uint32_t mask, int elem, int adjoint, i
 }
 
 // Steps of one DRT forward or adjoint over the dodecants of `mask`.
+// narrow: the volume is 8-bit (forward only); the first pass writes 16-bit
+// partial sums, later passes 32-bit (see drt_pass_fast's SB, DB).
 static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_float, int adjoint, int chunked,
-                     const Tuning& t, const DrtIO& io)
+                     const Tuning& t, const DrtIO& io, int narrow = 0)
 {
     const int n = ilog2_exact(N);
     const int elem = 4;
@@ -806,9 +819,17 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
     const int chunk_ws = chunked ? chunk_size(2 * per * elem, nd) : nd;
     const std::vector<PassGeom> P = drt_passes(N, t);
     const int np = (int)P.size();
-    // stage elements per dodecant of this tuning (pitches rounded to 32)
+    if (narrow && adjoint) return fail(DRT3D_EUNSUPPORTED, "8-bit volumes are taken by the forward only");
+    // storage bytes of pass i's source and destination, and the pitch of the
+    // stage it writes: columns start on 128-byte lines (32 elements, or 64 of
+    // the first stage's 16-bit ones)
+    auto src_bytes = [&](int i) { return !narrow ? 4 : i == 0 ? 1 : i == 1 ? 2 : 4; };
+    auto dst_bytes = [&](int i) { return !narrow || i == np - 1 ? 4 : i == 0 ? 2 : 4; };
+    auto pitch_of = [&](int i) { return dst_bytes(i) == 2 ? (P[i].E_out + 63) & ~63LL : round32(P[i].E_out); };
+    // stage elements per dodecant of this tuning
     long long per_t = 1;
-    for (int i = 0; i + 1 < np; ++i) per_t = std::max(per_t, (long long)N * N * round32(P[i].E_out));
+    for (int i = 0; i + 1 < np; ++i) per_t = std::max(per_t, (long long)N * N * pitch_of(i));
+    if (per_t > per) return fail(DRT3D_EUNSUPPORTED, "stage pitches of this tuning exceed the workspace bound");
     int chunk = (int)std::min<long long>(nd, chunk_ws * per / per_t);
     // whole layout groups per chunk when every group present has all four
     // dodecants: the first pass then shares each group's loads (xcd_run)
@@ -830,16 +851,19 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
 
     // forward: the y- and x-normal copies of the volume
     if (!adjoint) {
+        const int vb = narrow ? 1 : 4;
         if (has[1]) {  // V_Y[x][z][y] = vol[x][y][z]
             Step s; s.kind = S_TRANSPOSE; s.key = kKeyTransY; s.name = "transpose_in";
             s.t_in = io.in; s.t_out = V[1]; s.t_R = N; s.t_C = N; s.t_batches = N; s.t_add = 0;
-            s.bytes = 2.0 * vol_bytes;
+            s.t_bytes = vb;
+            s.bytes = 2.0 * vb * N * N * N;
             steps.push_back(s);
         }
         if (has[2]) {  // V_X[(y,z)][x] = vol[x][(y,z)]
             Step s; s.kind = S_TRANSPOSE; s.key = kKeyTransX; s.name = "transpose_in";
             s.t_in = io.in; s.t_out = V[2]; s.t_R = N; s.t_C = N * N; s.t_batches = 1; s.t_add = 0;
-            s.bytes = 2.0 * vol_bytes;
+            s.t_bytes = vb;
+            s.bytes = 2.0 * vb * N * N * N;
             steps.push_back(s);
         }
     }
@@ -862,6 +886,8 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             d.nslots = ns;
             d.E_in = adjoint ? g.E_out : g.E_in;
             d.E_out = adjoint ? g.E_in : g.E_out;
+            d.sb = adjoint ? 4 : src_bytes(pi);
+            d.db = adjoint ? 4 : dst_bytes(pi);
             const bool first = step == 0, last = step == np - 1;
             for (int s = 0; s < ns; ++s) {
                 const int k = dods[c0 + s];
@@ -880,7 +906,7 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             } else {
                 d.src = S[(step - 1) & 1];
                 d.src_slot_stride = per_t;
-                d.P_in = (int)round32(d.E_in);
+                d.P_in = adjoint ? (int)round32(d.E_in) : (int)pitch_of(pi - 1);
             }
             if (last && !adjoint) {
                 d.dst = io.out;
@@ -893,7 +919,7 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             } else {
                 d.dst = S[step & 1];
                 d.dst_slot_stride = per_t;
-                d.P_out = (int)round32(d.E_out);
+                d.P_out = adjoint ? (int)round32(d.E_out) : (int)pitch_of(pi);
             }
             const int K = g.Kx + g.Ky;
             int waves = std::min(t.waves, std::max(1, 1 << (K - 1)));
@@ -903,11 +929,12 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             const double cols = (double)N * N;
             char nm[32];
             snprintf(nm, sizeof nm, "drt_%s_p%d", adjoint ? "adj" : "fwd", pi + 1);
-            const int shape = g.Kx | (g.Ky << 4) | ((L >> 6) << 8);
+            const int shape = g.Kx | (g.Ky << 4) | ((L >> 6) << 8) | (d.sb << 16) | (d.db << 20);
             if (!(last && adjoint)) {
                 Step s; s.kind = S_DRT; s.key = kKeyPass + step; s.name = nm;
                 s.waves = waves; s.lds = lds; s.shape = shape;
-                s.bytes = (double)ns * cols * elem * (first && !adjoint ? N + d.E_out : d.E_in + d.E_out);
+                s.bytes = (double)ns * cols *
+                          ((first && !adjoint ? (double)N : (double)d.E_in) * d.sb + (double)d.E_out * d.db);
                 s.drt.push_back(d);
                 steps.push_back(s);
             } else {
@@ -1154,9 +1181,9 @@ static std::string program_signature(const Program& p, void* d_area)
     snprintf(buf, sizeof buf, "%p|%d|", d_area, p.is_float);
     sig += buf;
     for (const Launch& L : p.launches) {
-        snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%d:%zu:%d.%d.%d:%d%d%d%d;", L.kind, L.first, L.ndesc, L.total_wg,
-                 L.persistent, L.block, L.lds, L.fast_kx, L.fast_ky, L.fast_nch + 8 * L.fast_mode, L.djt_k, L.djt_ncc,
-                 L.djt_nco, L.djt_adj);
+        snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%d:%zu:%d.%d.%d:%d%d%d%d:%d%d%d;", L.kind, L.first, L.ndesc,
+                 L.total_wg, L.persistent, L.block, L.lds, L.fast_kx, L.fast_ky, L.fast_nch + 8 * L.fast_mode, L.djt_k,
+                 L.djt_ncc, L.djt_nco, L.djt_adj, L.fast_sb, L.fast_db, L.tr_bytes);
         sig += buf;
         if (L.kind == S_SUM) {
             snprintf(buf, sizeof buf, "%p>%p:%d:%d:%lld;", L.sum_in, L.sum_out, L.sum_parts, L.sum_accum, L.sum_n);
@@ -1272,7 +1299,8 @@ size_t djt3d_out_elems(int N, uint32_t mask)
 
 size_t drt3d_workspace_bytes(int N, uint32_t mask, int dtype)
 {
-    if (check_common(N, mask, dtype) != DRT3D_OK) return 0;
+    // 8-bit volumes use the int32 forward's workspace (their buffers are smaller)
+    if (check_common(N, mask, dtype == DRT3D_U8 ? DRT3D_I32 : dtype) != DRT3D_OK) return 0;
     return desc_area_bytes(S_DRT, N, mask, 1) + drt_ws_volume_bytes(N, mask, 4, 0, 1);
 }
 
@@ -1328,7 +1356,10 @@ size_t djt3d_adjoint_batched_workspace_bytes(int count, const int* Ns, uint32_t 
 static int drt_single(const void* in, void* out, int N, uint32_t mask, int dtype, void* ws, size_t ws_bytes,
                       void* stream, int adjoint)
 {
-    TRY(check_common(N, mask, dtype));
+    const int narrow = dtype == DRT3D_U8;
+    if (narrow && adjoint) return fail(DRT3D_EUNSUPPORTED, "8-bit data is taken by drt3d_forward only");
+    if (narrow && N < 32) return fail(DRT3D_EUNSUPPORTED, "8-bit volumes are taken for N >= 32 (got N = %d)", N);
+    TRY(check_common(N, mask, narrow ? DRT3D_I32 : dtype));
     TRY(check_ptr(in, adjoint ? "proj" : "vol"));
     TRY(check_ptr(out, adjoint ? "vol_out" : "out"));
     const size_t need = adjoint ? drt3d_adjoint_workspace_bytes(N, mask, dtype) : drt3d_workspace_bytes(N, mask, dtype);
@@ -1339,12 +1370,17 @@ static int drt_single(const void* in, void* out, int N, uint32_t mask, int dtype
     const Tuning t = get_tuning(N, is_float);
     DrtIO io{in, out, (char*)ws + desc_area_bytes(S_DRT, N, mask, 1)};
     std::vector<std::vector<Step>> vols(1);
-    TRY(drt_steps(vols[0], N, mask, is_float, adjoint, 1, t, io));
+    TRY(drt_steps(vols[0], N, mask, is_float, adjoint, 1, t, io, narrow));
     Program prog;
     prog.is_float = is_float;
     build_program(prog, vols, false);
     if (prog.desc_bytes() > desc_area_bytes(S_DRT, N, mask, 1))
         return fail(DRT3D_EINVAL, "internal: descriptor area too small");
+    if (narrow)  // narrow storage exists in the shape-specialised passes only
+        for (const Launch& L : prog.launches)
+            if (L.kind == S_DRT && L.fast_kx < 0)
+                return fail(DRT3D_EUNSUPPORTED, "8-bit volumes: tuning %s has a pass without a narrow kernel",
+                            tuning_to_string(t).c_str());
     return execute(prog, ws, (hipStream_t)stream, di, 0);
 }
 

@@ -121,6 +121,22 @@ def test_inverse_argument_checks():
         assert word in L.drt3d_last_error().decode()
 
 
+def test_u8_is_a_forward_only_dtype():
+    """8-bit volumes: the forward takes them (N >= 32, the int32 workspace);
+    every other entry point rejects the dtype before any device work."""
+    L = _lib()
+    A = _fake(1 << 20)
+    EUNSUPPORTED = -4
+    assert L.drt3d_workspace_bytes(64, 0xFFF, 2) == L.drt3d_workspace_bytes(64, 0xFFF, 0) > 0
+    assert L.drt3d_adjoint_workspace_bytes(64, 0xFFF, 2) == 0
+    assert L.djt3d_workspace_bytes(64, 0xFFF, 2) == 0
+    ws = L.drt3d_workspace_bytes(16, 0xFFF, 0)
+    assert L.drt3d_forward(A, A, 16, 0xFFF, 2, A, ws, None) == EUNSUPPORTED
+    assert "N >= 32" in L.drt3d_last_error().decode()
+    assert L.drt3d_adjoint(A, A, 64, 0xFFF, 2, A, 1 << 40, None) == EUNSUPPORTED
+    assert L.djt3d_forward(A, A, 64, 0xFFF, 2, A, 1 << 40, None) == EINVAL
+
+
 def test_batched_argument_checks():
     L = _lib()
     A = (1 << 20)

@@ -1,0 +1,62 @@
+"""The DRT of 8-bit volumes with narrow storage (DRT3D_U8): 1-byte volume
+copies, 16-bit first-stage partial sums, 32-bit afterwards. The result must be
+the int32 transform of the same values bit for bit, at every size with
+built-in tunings (each of their pass shapes) and at the benchmark's N = 512."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads
+from tests.gpu_util import announce, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2501_13664_amd import api
+    return api
+
+
+@pytest.mark.parametrize("N", [32, 64, 128, 256])
+def test_u8_forward_equals_int32_forward(N):
+    import torch
+    api = _api()
+    rng = np.random.default_rng(80 + N)
+    for name, vol in (("random", rng.integers(0, 256, size=(N, N, N))),
+                      ("all 255", np.full((N, N, N), 255))):
+        v8 = to_dev(vol.astype(np.uint8))
+        v32 = to_dev(vol.astype(np.int32))
+        announce("u8 forward N=%d %s" % (N, name))
+        got = api.drt3d_forward(v8)
+        assert got.dtype == torch.int32
+        assert torch.equal(got, api.drt3d_forward(v32)), "N=%d %s" % (N, name)
+
+
+def test_u8_forward_matches_the_oracle_and_masks():
+    import torch
+    api = _api()
+    N = 32
+    vol = workloads.uniform_int_cube(N, 0, 255, seed=1)
+    ref = O.wrap_int32(O.rec_drt(vol))
+    announce("u8 forward N=32 vs oracle")
+    assert np.array_equal(api.drt3d_forward(to_dev(vol.astype(np.uint8))).cpu().numpy(), ref)
+    for mask in (0x001, 0x0F0, 0b101001010010):
+        sel = [k for k in range(12) if (mask >> k) & 1]
+        announce("u8 forward N=32 mask=%#x" % mask)
+        got = api.drt3d_forward(to_dev(vol.astype(np.uint8)), mask).cpu().numpy()
+        assert np.array_equal(got, ref[sel])
+
+
+def test_u8_forward_n512_benchmark_cube():
+    """The benchmark's cube (values 0, 1 and 16) through the narrow path equals
+    its int32 forward, all 12 dodecants, every element."""
+    import torch
+    api = _api()
+    vol = workloads.point_cloud_with_planes(512, seed=2)
+    announce("u8 forward N=512 int32 reference")
+    ref = api.drt3d_forward(to_dev(vol))
+    announce("u8 forward N=512 narrow")
+    got = api.drt3d_forward(to_dev(vol.astype(np.uint8)))
+    assert torch.equal(got, ref)
+    del ref, got
+    torch.cuda.empty_cache()
