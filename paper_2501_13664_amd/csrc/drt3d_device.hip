@@ -44,6 +44,12 @@ hipError_t set_drt_lds_limit(int is_float, size_t bytes)
                     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
                     if (e != hipSuccess) return e;
                 }
+    for (int nc = 1; nc <= 6; ++nc) {
+        const void* k = drt_adj_group_kernel(is_float, nc);
+        if (!k) continue;
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
     const int narrow[4][3] = {{0, 1, 2}, {0, 2, 4}, {1, 2, 4}, {1, 1, 4}};  // (mode, sb, db)
     if (!is_float)
         for (auto& sh : shapes)
@@ -91,6 +97,15 @@ hipError_t launch_djt_pass(int is_float, int K, int ncc, int nco, const DjtDesc*
                            long long total_wg, int grid, size_t lds_bytes, hipStream_t s)
 {
     const void* k = djt_pass_kernel_ptr(is_float, K, ncc, nco);
+    if (!k) return hipErrorInvalidValue;
+    void* args[] = {&d_descs, &ndesc, &total_wg};
+    return hipLaunchKernel(k, dim3(grid), dim3(512), args, lds_bytes, s);
+}
+
+hipError_t launch_drt_adj_group(int is_float, int nch, const DrtDesc* d_descs, int ndesc, long long total_wg,
+                                int grid, size_t lds_bytes, hipStream_t s)
+{
+    const void* k = drt_adj_group_kernel(is_float, nch);
     if (!k) return hipErrorInvalidValue;
     void* args[] = {&d_descs, &ndesc, &total_wg};
     return hipLaunchKernel(k, dim3(grid), dim3(512), args, lds_bytes, s);

@@ -59,6 +59,20 @@ const void* DRT3D_CAT(drt_fast_kernel_narrow_, DRT3D_KX, DRT3D_KY)(int nch, int 
     return nullptr;
 }
 
+#if DRT3D_KX == 3 && DRT3D_KY == 3
+// The adjoint's last pass fused over each volume layout group (3.3 only).
+const void* drt_adj_group_kernel(int is_float, int nch)
+{
+#define DRT3D_NC(NC)                                                                                   \
+    if (nch == NC)                                                                                     \
+        return is_float ? reinterpret_cast<const void*>(&fast::drt_adj_last_group<float, NC>)          \
+                        : reinterpret_cast<const void*>(&fast::drt_adj_last_group<uint32_t, NC>);
+    DRT3D_NC(1) DRT3D_NC(2) DRT3D_NC(3) DRT3D_NC(4) DRT3D_NC(5) DRT3D_NC(6)
+#undef DRT3D_NC
+    return nullptr;
+}
+#endif
+
 // mode: 0 forward into a stage buffer, 1 the forward's last pass, 2 adjoint;
 // waves: 8, or 16 for the 3.3 shape
 const void* DRT3D_CAT(drt_fast_kernel_, DRT3D_KX, DRT3D_KY)(int is_float, int nch, int mode, int waves)

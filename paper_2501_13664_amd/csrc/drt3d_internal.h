@@ -45,6 +45,9 @@ struct DrtDesc {
     // time), sharing its loads through that XCD's L2
     int xcd_run;
     int sb, db;            // bytes per element of the source and destination in HBM (4, or narrow storage)
+    // adjoint's last pass, one work item per volume layout group and block:
+    // slots 4g .. 4g+3 are group g's four dodecants (drt_adj_last_group)
+    int fused_group;
     int phys[kMaxSlots];   // slot -> slot index inside the source (stage buffer or projections)
     int dphys[kMaxSlots];  // slot -> slot index inside the destination (dst_mode 0)
     int accum[kMaxSlots];  // dst_mode 1: add into the volume (1) or overwrite (0)
@@ -131,6 +134,10 @@ hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int mode, int 
                            int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s, int sb = 4,
                            int db = 4);
 hipError_t launch_transpose_u8(const TransDesc* d_descs, int ndesc, long long total_wg, hipStream_t s);
+// The adjoint's last pass fused over layout groups (3.3 passes, eight wavefronts).
+const void* drt_adj_group_kernel(int is_float, int nch);
+hipError_t launch_drt_adj_group(int is_float, int nch, const DrtDesc* d_descs, int ndesc, long long total_wg,
+                                int grid, size_t lds_bytes, hipStream_t s);
 
 // Iterative inverse (float32): filter, residual, restriction, prolongation,
 // and the vector steps of the power iteration.

@@ -810,6 +810,154 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
     }
 }
 
+// The adjoint's last pass (the transpose of the forward's first pass: stages
+// 0..2 of both axes) fused over a volume layout group. The four dodecants of
+// a group write the same layout, their frames differ by a rotation or
+// reflection of the slope plane, and they share the displacement axis (same
+// sign and origin), so their 8 x 8 column blocks and displacement tiles map
+// onto the same physical block and z range. A work item owns one physical
+// block: for each tile it runs the four dodecants' transposed stages in turn
+// (each loaded into LDS ahead of time, the next while the current one runs),
+// adds each result into registers in physical column order, and writes the
+// block once. The volume is written once instead of once per dodecant with
+// three read-backs. Slots 4g..4g+3 of the descriptor are group g's dodecants.
+// Its sums and tails take ~40 more registers than a plain pass: 128 per lane
+// (4 waves per SIMD, two work groups per CU) keeps them out of scratch.
+template <typename T, int NCH>
+__global__ void __launch_bounds__(512, 4)
+drt_adj_last_group(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
+{
+    constexpr int KX = 3, KY = 3, NW = 8, NS = 64, SPW = 8, L = 64 * NCH, NDOD = 4;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // loading side (frame coordinates): the wave owns slots p = wave + 8 i, px = wave
+    const int rpx = bitrev(wave, KX);
+
+    for (long long wg = blockIdx.x; wg < total_wg; wg += gridDim.x) {
+        const DrtDesc* d = descs + find_desc_drt(descs, ndesc, wg);
+        const int local = (int)(wg - d->wg_begin);
+        const int n = d->n, N = d->N;
+        const int G = N >> 3;
+        const int lg = 2 * (n - 3);
+        const int blk = local & ((1 << lg) - 1);
+        const int grp = local >> lg;
+        const int b1 = blk / G, b2 = blk - b1 * G;  // physical block along the layout's first and second index
+        const int T_ = d->T, Lp = d->Lp, pad = Lp - L;
+        const int ntiles = min(d->ntiles, (d->E_out + T_ - 1) / T_);
+        const FrameMap f0 = d->fm[NDOD * grp];
+        const int dsd = f0.sd;                        // shared by the group
+        const int zb = dsd > 0 ? 0 : N - 1;           // column origin along the displacement axis
+        const __amdgpu_buffer_rsrc_t rs_dst = make_rsrc(reinterpret_cast<T*>(d->vdst[f0.group]), N * N * N);
+
+        // frame view of dodecant r: its block of the physical block, and the
+        // frame position (px, py) of physical position (pa, pb) in the block
+        auto frame_block = [&](const FrameMap& f, int& bx, int& by) {
+            const bool first = f.sx == N * N || f.sx == -N * N;
+            bx = first ? (f.sx > 0 ? b1 : G - 1 - b1) : (f.sx > 0 ? b2 : G - 1 - b2);
+            by = first ? (f.sy > 0 ? b2 : G - 1 - b2) : (f.sy > 0 ? b1 : G - 1 - b1);
+        };
+        auto frame_pos = [&](const FrameMap& f, int pa, int pb) {
+            const bool first = f.sx == N * N || f.sx == -N * N;
+            const int qx = first ? (f.sx > 0 ? pa : 7 - pa) : (f.sx > 0 ? pb : 7 - pb);
+            const int qy = first ? (f.sy > 0 ? pb : 7 - pb) : (f.sy > 0 ? pa : 7 - pa);
+            return qx + 8 * qy;  // LDS slot
+        };
+
+        for (int p = wave; p <= NS; p += NW)
+            if (lane < pad) lds[p * Lp + lane] = zero_of<T>();
+
+        uint32_t v[SPW][NCH];
+        T acc[SPW][NCH + 1];  // this tile's sums over the dodecants, per physical column and store chunk
+        uint32_t carry[SPW];  // the previous tile's tail sums (lane k: displacement fbeg + k)
+        T ncarry[SPW];        // this tile's tail sums
+#pragma unroll
+        for (int i = 0; i < SPW; ++i) carry[i] = 0u;
+
+        // step j = tile * 4 + r loads dodecant r's slope columns for the tile
+        auto issue_loads = [&](int j) {
+            const int tile = j >> 2, r = j & 3;
+            const int s = NDOD * grp + r;
+            const FrameMap f = d->fm[s];
+            int bx, by;
+            frame_block(f, bx, by);
+            const char* base = reinterpret_cast<const char*>(d->src) + 4LL * d->phys[s] * d->src_slot_stride;
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc_bytes(base, 4 * (int)d->src_slot_stride);
+            const int so = (((rpx + 8 * bx) << n) + 8 * by) * d->P_in;
+            const int d0 = tile * T_;
+#pragma unroll
+            for (int i = 0; i < SPW; ++i) {
+                const int colo = so + bitrev(i, KY) * d->P_in;
+                const int dl = d0 + lane;
+                const int ob = 4 * (colo + dl);
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const bool in = (unsigned)(dl + 64 * c) < (unsigned)d->E_in;
+                    v[i][c] = bload(rs, in ? ob + 256 * c : -1);
+                }
+            }
+        };
+
+        const int nsteps = ntiles * NDOD;
+        issue_loads(0);
+        for (int j = 0; j < nsteps; ++j) {
+            const int tile = j >> 2, r = j & 3;
+            const int d0 = tile * T_;
+            const bool last_tile = tile + 1 == ntiles;
+#pragma unroll
+            for (int i = 0; i < SPW; ++i) {
+                T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + lane;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) sl[64 * c] = from_bits<T>(v[i][c]);
+            }
+            __syncthreads();
+            if (j + 1 < nsteps) issue_loads(j + 1);
+            run_stages<T, NCH>(lds, Lp, pad, NCH, KX, KY, 1, wave, NW, lane);
+            __syncthreads();
+            // the wave's physical columns: (pa, pb) = (wave, i); a column's
+            // line-aligned window [fbeg, fend) is the same for every dodecant
+            const FrameMap f = d->fm[NDOD * grp + r];
+#pragma unroll
+            for (int i = 0; i < SPW; ++i) {
+                const int colo = (8 * b1 + wave) * N * N + (8 * b2 + i) * N + zb;
+                const int mis = dsd > 0 ? (colo & 31) : ((colo + 1) & 31);
+                auto line_floor = [&](int x) { return dsd > 0 ? x - ((mis + x) & 31) : x - ((x - mis) & 31); };
+                const int fbeg = d0 <= 0 ? d0 : line_floor(d0);
+                const int fend = last_tile ? d0 + T_ : line_floor(d0 + T_);
+                const int cnt = fend - fbeg;
+                const T* sl = lds + slot_offset(frame_pos(f, wave, i), Lp, pad) - d0;  // sl[dd]: displacement dd
+#pragma unroll
+                for (int c = 0; c < NCH + 1; ++c) {
+                    const int k = 64 * c + lane;
+                    const int dd = fbeg + k;
+                    const T x = k < cnt && dd >= d0 ? sl[dd] : zero_of<T>();
+                    acc[i][c] = r == 0 ? x : acc[i][c] + x;
+                }
+                const int tail = d0 + T_ - fend;
+                const T t = !last_tile && lane < tail ? sl[fend + lane] : zero_of<T>();
+                ncarry[i] = r == 0 ? t : ncarry[i] + t;
+                if (r == NDOD - 1) {
+                    // every dodecant is in: one line-aligned store of the sums
+                    const int fl = fbeg + lane;
+                    const int ob = 4 * colo + (dsd > 0 ? 4 * fl : -4 * fl);
+#pragma unroll
+                    for (int c = 0; c < NCH + 1; ++c) {
+                        const int k = 64 * c + lane;
+                        const int dd = fbeg + k;
+                        if (k < cnt && (unsigned)dd < (unsigned)N) {
+                            const T val = dd < d0 ? from_bits<T>(carry[i]) : acc[i][c];
+                            bstore(rs_dst, ob + (dsd > 0 ? 256 * c : -256 * c), to_bits(val));
+                        }
+                    }
+                    carry[i] = to_bits(ncarry[i]);
+                }
+            }
+            __syncthreads();  // the LDS is free for the next dodecant
+        }
+    }
+}
+
 }  // namespace fast
 
 // ---------------------------------------------------------------------------

@@ -405,6 +405,7 @@ struct Launch {
     int fast_mode = 0;                              // ... 0 forward, 1 forward last pass, 2 adjoint
     int fast_sb = 4, fast_db = 4;                   // ... storage bytes of its source and destination
     int tr_bytes = 4;                               // transposes: element bytes
+    int adj_group = 0;                              // DRT: drt_adj_last_group (fast_nch chunks)
     int djt_k = 0, djt_ncc = 0, djt_nco = 0;        // DJT: stages fused per pass, LDS/output row chunks
     int djt_adj = 0;                                // DJT: the pass's transpose
     const void* sum_in = nullptr;                   // S_SUM
@@ -522,7 +523,8 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
             if (s->kind == S_DRT) {
                 for (DrtDesc d : s->drt) {
                     d.wg_begin = wg;
-                    wg += (long long)d.nslots * d.groups_x * d.groups_y;
+                    // a fused adjoint item covers a group's four dodecants
+                    wg += (long long)(d.fused_group ? d.nslots / 4 : d.nslots) * d.groups_x * d.groups_y;
                     prog.drt.push_back(d);
                 }
             } else {
@@ -543,7 +545,10 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
         L.block = 64 * waves;
         L.lds = lds;
         L.bytes = bytes;
-        if (s0->kind == S_DRT && (L.block == 512 || L.block == 1024)) {
+        if (s0->kind == S_DRT && prog.drt[L.first].fused_group) {
+            L.adj_group = 1;
+            L.fast_nch = prog.drt[L.first].L >> 6;
+        } else if (s0->kind == S_DRT && (L.block == 512 || L.block == 1024)) {
             // one shape across the launch's descriptors -> specialised kernel
             const DrtDesc& f = prog.drt[L.first];
             bool same = true, final_pass = true;
@@ -637,7 +642,10 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
             if (L.lds > (size_t)di.max_lds)
                 return fail(DRT3D_EINVAL, "%s needs %zu bytes of LDS, the device allows %d", L.name.c_str(), L.lds,
                             di.max_lds);
-            if (L.fast_kx >= 0)
+            if (L.adj_group)
+                e = launch_drt_adj_group(p.is_float, L.fast_nch, d_drt + L.first, L.ndesc, L.total_wg,
+                                         grid_for(L.total_wg, di, L.persistent), L.lds, s);
+            else if (L.fast_kx >= 0)
                 e = launch_drt_fast(p.is_float, L.fast_kx, L.fast_ky, L.fast_nch, L.fast_mode, L.block / 64, d_drt + L.first, L.ndesc,
                                     L.total_wg, grid_for(L.total_wg, di, L.persistent), L.lds, s, L.fast_sb, L.fast_db);
             else
@@ -802,16 +810,6 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
     for (int g = 0; g < 3; ++g)
         for (int k = 0; k < 12; ++k)
             if (((mask >> k) & 1) && drt_group(k) == g) { dods[nd2++] = k; ++gcount[g]; }
-    if (adjoint) {
-        // the adjoint's last pass adds the dodecants of one group into one
-        // volume in rounds, one dodecant of each group per round: mixing the
-        // groups inside a chunk makes fewer, fuller rounds
-        int by[3][4], c[3] = {0, 0, 0}, q = 0;
-        for (int i = 0; i < nd; ++i) { const int g = drt_group(dods[i]); by[g][c[g]++] = dods[i]; }
-        for (int r = 0; r < 4; ++r)
-            for (int g = 0; g < 3; ++g)
-                if (r < c[g]) dods[q++] = by[g][r];
-    }
     bool has[3] = {false, false, false};
     for (int i = 0; i < nd; ++i) has[drt_group(dods[i])] = true;
     const size_t vol_bytes = (size_t)N * N * N * elem;
@@ -836,6 +834,29 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
     const bool runs4 = (gcount[0] == 0 || gcount[0] == 4) && (gcount[1] == 0 || gcount[1] == 4) &&
                        (gcount[2] == 0 || gcount[2] == 4);
     if (runs4 && chunk >= 4 && !adjoint) chunk -= chunk % 4;
+    // The adjoint's last pass (the forward's first, transposed) adds the
+    // dodecants of each volume layout group into one volume. When every group
+    // present is whole in a single chunk and that pass is a 3.3 pass of eight
+    // wavefronts, one fused launch sums each group's four dodecants per block
+    // (slots in group order); otherwise it runs in rounds, one dodecant of
+    // each group per round, and mixing the groups inside a chunk makes fewer,
+    // fuller rounds.
+    bool fuse_last = false;
+    if (adjoint) {
+        const PassGeom& g0 = P[0];
+        int T0, H0, L0, nt0;
+        const int w0 = std::min(t.waves, std::max(1, 1 << (g0.Kx + g0.Ky - 1)));
+        fuse_last = runs4 && chunk == nd && g0.Kx == 3 && g0.Ky == 3 && w0 == 8 &&
+                    choose_tiles(g0, 1, t.lds_elems, T0, H0, L0, nt0) && (L0 & 63) == 0 && (L0 >> 6) <= 4 &&
+                    drt_adj_group_kernel(is_float, L0 >> 6) != nullptr;  // wider tiles would spill its sums
+        if (!fuse_last) {
+            int by[3][4], c[3] = {0, 0, 0}, q = 0;
+            for (int i = 0; i < nd; ++i) { const int g = drt_group(dods[i]); by[g][c[g]++] = dods[i]; }
+            for (int r = 0; r < 4; ++r)
+                for (int g = 0; g < 3; ++g)
+                    if (r < c[g]) dods[q++] = by[g][r];
+        }
+    }
 
     char* w = io.ws;
     void* V[3] = {nullptr, nullptr, nullptr};
@@ -930,7 +951,14 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             char nm[32];
             snprintf(nm, sizeof nm, "drt_%s_p%d", adjoint ? "adj" : "fwd", pi + 1);
             const int shape = g.Kx | (g.Ky << 4) | ((L >> 6) << 8) | (d.sb << 16) | (d.db << 20);
-            if (!(last && adjoint)) {
+            if (last && adjoint && fuse_last) {
+                d.fused_group = 1;
+                Step s; s.kind = S_DRT; s.key = kKeyRound; s.name = nm;
+                s.waves = 8; s.lds = lds; s.shape = shape | (1 << 24);
+                s.bytes = cols * elem * ((double)ns * d.E_in + (double)(ns / 4) * d.E_out);
+                s.drt.push_back(d);
+                steps.push_back(s);
+            } else if (!(last && adjoint)) {
                 Step s; s.kind = S_DRT; s.key = kKeyPass + step; s.name = nm;
                 s.waves = waves; s.lds = lds; s.shape = shape;
                 s.bytes = (double)ns * cols *
@@ -1183,7 +1211,7 @@ static std::string program_signature(const Program& p, void* d_area)
     for (const Launch& L : p.launches) {
         snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%d:%zu:%d.%d.%d:%d%d%d%d:%d%d%d;", L.kind, L.first, L.ndesc,
                  L.total_wg, L.persistent, L.block, L.lds, L.fast_kx, L.fast_ky, L.fast_nch + 8 * L.fast_mode, L.djt_k,
-                 L.djt_ncc, L.djt_nco, L.djt_adj, L.fast_sb, L.fast_db, L.tr_bytes);
+                 L.djt_ncc, L.djt_nco, L.djt_adj, L.fast_sb, L.fast_db, L.tr_bytes + 8 * L.adj_group);
         sig += buf;
         if (L.kind == S_SUM) {
             snprintf(buf, sizeof buf, "%p>%p:%d:%d:%lld;", L.sum_in, L.sum_out, L.sum_parts, L.sum_accum, L.sum_n);
