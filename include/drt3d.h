@@ -224,7 +224,10 @@ int drt3d_pass_times(char* names /* cap x 32 chars */, double* ms, long long* la
 int drt3d_frame_map(int k, int N, int kind, int out[5]);
 /* Text description of the launches one call would make (op 0: drt3d_forward,
  * 1: drt3d_adjoint, 2: djt3d_forward, 3: djt3d_adjoint), one line per launch:
- * "name kind=<k> wg=<work groups> block=<threads> lds=<bytes> bytes=<algorithmic>".
+ * "name kind=<k> wg=<work groups> block=<threads> lds=<bytes> bytes=<algorithmic>
+ * kernel=<K>", where K names the DRT pass kernel: "fastA.BxW" (the pass kernel
+ * specialised for A.B stages and W wavefronts), "groupA.BxW" (the adjoint's last
+ * pass fused over each volume layout group), "generic", or "-" for other kinds.
  * Returns the number of launches, or a negative status. */
 int drt3d_plan_text(int op, int N, uint32_t mask, int dtype, char* buf, size_t cap);
 

@@ -44,12 +44,14 @@ hipError_t set_drt_lds_limit(int is_float, size_t bytes)
                     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
                     if (e != hipSuccess) return e;
                 }
-    for (int nc = 1; nc <= 6; ++nc) {
-        const void* k = drt_adj_group_kernel(is_float, nc);
-        if (!k) continue;
-        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-        if (e != hipSuccess) return e;
-    }
+    for (int K = 2; K <= 3; ++K)
+        for (int nc = 1; nc <= 6; ++nc)
+            for (int waves : {8, 16}) {
+                const void* k = drt_adj_group_kernel(is_float, K, nc, waves);
+                if (!k) continue;
+                hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+                if (e != hipSuccess) return e;
+            }
     const int narrow[4][3] = {{0, 1, 2}, {0, 2, 4}, {1, 2, 4}, {1, 1, 4}};  // (mode, sb, db)
     if (!is_float)
         for (auto& sh : shapes)
@@ -102,13 +104,20 @@ hipError_t launch_djt_pass(int is_float, int K, int ncc, int nco, const DjtDesc*
     return hipLaunchKernel(k, dim3(grid), dim3(512), args, lds_bytes, s);
 }
 
-hipError_t launch_drt_adj_group(int is_float, int nch, const DrtDesc* d_descs, int ndesc, long long total_wg,
-                                int grid, size_t lds_bytes, hipStream_t s)
+const void* drt_adj_group_kernel(int is_float, int K, int nch, int waves)
 {
-    const void* k = drt_adj_group_kernel(is_float, nch);
+    if (K == 3) return drt_adj_group_kernel_3_3(is_float, nch, waves);
+    if (K == 2) return drt_adj_group_kernel_2_2(is_float, nch, waves);
+    return nullptr;
+}
+
+hipError_t launch_drt_adj_group(int is_float, int K, int nch, int waves, const DrtDesc* d_descs, int ndesc,
+                                long long total_wg, int grid, size_t lds_bytes, hipStream_t s)
+{
+    const void* k = drt_adj_group_kernel(is_float, K, nch, waves);
     if (!k) return hipErrorInvalidValue;
     void* args[] = {&d_descs, &ndesc, &total_wg};
-    return hipLaunchKernel(k, dim3(grid), dim3(512), args, lds_bytes, s);
+    return hipLaunchKernel(k, dim3(grid), dim3(64 * waves), args, lds_bytes, s);
 }
 
 hipError_t launch_transpose_u8(const TransDesc* d_descs, int ndesc, long long total_wg, hipStream_t s)

@@ -59,16 +59,23 @@ const void* DRT3D_CAT(drt_fast_kernel_narrow_, DRT3D_KX, DRT3D_KY)(int nch, int 
     return nullptr;
 }
 
-#if DRT3D_KX == 3 && DRT3D_KY == 3
-// The adjoint's last pass fused over each volume layout group (3.3 only).
-const void* drt_adj_group_kernel(int is_float, int nch)
+#if DRT3D_KX == DRT3D_KY
+// The adjoint's last pass fused over each volume layout group (square shapes).
+template <typename T, int NW>
+static const void* adj_group_nw(int nch)
 {
-#define DRT3D_NC(NC)                                                                                   \
-    if (nch == NC)                                                                                     \
-        return is_float ? reinterpret_cast<const void*>(&fast::drt_adj_last_group<float, NC>)          \
-                        : reinterpret_cast<const void*>(&fast::drt_adj_last_group<uint32_t, NC>);
+#define DRT3D_NC(NC) \
+    if (nch == NC) return reinterpret_cast<const void*>(&fast::drt_adj_last_group<T, DRT3D_KX, NC, NW>);
     DRT3D_NC(1) DRT3D_NC(2) DRT3D_NC(3) DRT3D_NC(4) DRT3D_NC(5) DRT3D_NC(6)
 #undef DRT3D_NC
+    return nullptr;
+}
+
+const void* DRT3D_CAT(drt_adj_group_kernel_, DRT3D_KX, DRT3D_KY)(int is_float, int nch, int waves)
+{
+    if (waves == 8) return is_float ? adj_group_nw<float, 8>(nch) : adj_group_nw<uint32_t, 8>(nch);
+    if (kWide && waves == 16)
+        return is_float ? adj_group_nw<float, kWide ? 16 : 8>(nch) : adj_group_nw<uint32_t, kWide ? 16 : 8>(nch);
     return nullptr;
 }
 #endif

@@ -134,10 +134,13 @@ hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int mode, int 
                            int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s, int sb = 4,
                            int db = 4);
 hipError_t launch_transpose_u8(const TransDesc* d_descs, int ndesc, long long total_wg, hipStream_t s);
-// The adjoint's last pass fused over layout groups (3.3 passes, eight wavefronts).
-const void* drt_adj_group_kernel(int is_float, int nch);
-hipError_t launch_drt_adj_group(int is_float, int nch, const DrtDesc* d_descs, int ndesc, long long total_wg,
-                                int grid, size_t lds_bytes, hipStream_t s);
+// The adjoint's last pass fused over layout groups (square K.K passes, K = 2
+// or 3; eight wavefronts, or sixteen for 3.3).
+const void* drt_adj_group_kernel_3_3(int is_float, int nch, int waves);
+const void* drt_adj_group_kernel_2_2(int is_float, int nch, int waves);
+const void* drt_adj_group_kernel(int is_float, int K, int nch, int waves);
+hipError_t launch_drt_adj_group(int is_float, int K, int nch, int waves, const DrtDesc* d_descs, int ndesc,
+                                long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
 
 // Iterative inverse (float32): filter, residual, restriction, prolongation,
 // and the vector steps of the power iteration.

@@ -823,24 +823,29 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 // three read-backs. Slots 4g..4g+3 of the descriptor are group g's dodecants.
 // Its sums and tails take ~40 more registers than a plain pass: 128 per lane
 // (4 waves per SIMD, two work groups per CU) keeps them out of scratch.
-template <typename T, int NCH>
-__global__ void __launch_bounds__(512, 4)
+// K: stages per axis of the pass (blocks of B x B columns, B = 2^K); NW:
+// wavefronts, a multiple of B (wave w owns slots p = w + NW i, whose x index
+// w mod B is fixed per wave, as in drt_pass_fast).
+template <typename T, int K, int NCH, int NW>
+__global__ void __launch_bounds__(64 * NW, 4)
 drt_adj_last_group(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 {
-    constexpr int KX = 3, KY = 3, NW = 8, NS = 64, SPW = 8, L = 64 * NCH, NDOD = 4;
+    constexpr int B = 1 << K, NS = B * B, SPW = NS / NW, L = 64 * NCH, NDOD = 4;
+    static_assert(NW % B == 0 && NS % NW == 0, "slots per wave");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    // loading side (frame coordinates): the wave owns slots p = wave + 8 i, px = wave
-    const int rpx = bitrev(wave, KX);
+    const int px = wave & (B - 1);  // x index of the wave's slots (frame side) and columns (physical side)
+    const int rpx = bitrev(px, K);
+    auto y_of = [&](int i) { return (wave >> K) + i * (NW >> K); };
 
     for (long long wg = blockIdx.x; wg < total_wg; wg += gridDim.x) {
         const DrtDesc* d = descs + find_desc_drt(descs, ndesc, wg);
         const int local = (int)(wg - d->wg_begin);
         const int n = d->n, N = d->N;
-        const int G = N >> 3;
-        const int lg = 2 * (n - 3);
+        const int G = N >> K;
+        const int lg = 2 * (n - K);
         const int blk = local & ((1 << lg) - 1);
         const int grp = local >> lg;
         const int b1 = blk / G, b2 = blk - b1 * G;  // physical block along the layout's first and second index
@@ -852,17 +857,17 @@ drt_adj_last_group(const DrtDesc* __restrict__ descs, int ndesc, long long total
         const __amdgpu_buffer_rsrc_t rs_dst = make_rsrc(reinterpret_cast<T*>(d->vdst[f0.group]), N * N * N);
 
         // frame view of dodecant r: its block of the physical block, and the
-        // frame position (px, py) of physical position (pa, pb) in the block
+        // LDS slot of physical position (pa, pb) in the block
         auto frame_block = [&](const FrameMap& f, int& bx, int& by) {
             const bool first = f.sx == N * N || f.sx == -N * N;
             bx = first ? (f.sx > 0 ? b1 : G - 1 - b1) : (f.sx > 0 ? b2 : G - 1 - b2);
             by = first ? (f.sy > 0 ? b2 : G - 1 - b2) : (f.sy > 0 ? b1 : G - 1 - b1);
         };
-        auto frame_pos = [&](const FrameMap& f, int pa, int pb) {
+        auto frame_slot = [&](const FrameMap& f, int pa, int pb) {
             const bool first = f.sx == N * N || f.sx == -N * N;
-            const int qx = first ? (f.sx > 0 ? pa : 7 - pa) : (f.sx > 0 ? pb : 7 - pb);
-            const int qy = first ? (f.sy > 0 ? pb : 7 - pb) : (f.sy > 0 ? pa : 7 - pa);
-            return qx + 8 * qy;  // LDS slot
+            const int qx = first ? (f.sx > 0 ? pa : B - 1 - pa) : (f.sx > 0 ? pb : B - 1 - pb);
+            const int qy = first ? (f.sy > 0 ? pb : B - 1 - pb) : (f.sy > 0 ? pa : B - 1 - pa);
+            return qx + B * qy;
         };
 
         for (int p = wave; p <= NS; p += NW)
@@ -884,11 +889,11 @@ drt_adj_last_group(const DrtDesc* __restrict__ descs, int ndesc, long long total
             frame_block(f, bx, by);
             const char* base = reinterpret_cast<const char*>(d->src) + 4LL * d->phys[s] * d->src_slot_stride;
             const __amdgpu_buffer_rsrc_t rs = make_rsrc_bytes(base, 4 * (int)d->src_slot_stride);
-            const int so = (((rpx + 8 * bx) << n) + 8 * by) * d->P_in;
+            const int so = (((rpx + B * bx) << n) + B * by) * d->P_in;
             const int d0 = tile * T_;
 #pragma unroll
             for (int i = 0; i < SPW; ++i) {
-                const int colo = so + bitrev(i, KY) * d->P_in;
+                const int colo = so + bitrev(y_of(i), K) * d->P_in;
                 const int dl = d0 + lane;
                 const int ob = 4 * (colo + dl);
 #pragma unroll
@@ -913,20 +918,21 @@ drt_adj_last_group(const DrtDesc* __restrict__ descs, int ndesc, long long total
             }
             __syncthreads();
             if (j + 1 < nsteps) issue_loads(j + 1);
-            run_stages<T, NCH>(lds, Lp, pad, NCH, KX, KY, 1, wave, NW, lane);
+            run_stages<T, NCH>(lds, Lp, pad, NCH, K, K, 1, wave, NW, lane);
             __syncthreads();
-            // the wave's physical columns: (pa, pb) = (wave, i); a column's
+            // the wave's physical columns (pa, pb) = (px, y_of(i)); a column's
             // line-aligned window [fbeg, fend) is the same for every dodecant
             const FrameMap f = d->fm[NDOD * grp + r];
 #pragma unroll
             for (int i = 0; i < SPW; ++i) {
-                const int colo = (8 * b1 + wave) * N * N + (8 * b2 + i) * N + zb;
+                const int pb = y_of(i);
+                const int colo = (B * b1 + px) * N * N + (B * b2 + pb) * N + zb;
                 const int mis = dsd > 0 ? (colo & 31) : ((colo + 1) & 31);
                 auto line_floor = [&](int x) { return dsd > 0 ? x - ((mis + x) & 31) : x - ((x - mis) & 31); };
                 const int fbeg = d0 <= 0 ? d0 : line_floor(d0);
                 const int fend = last_tile ? d0 + T_ : line_floor(d0 + T_);
                 const int cnt = fend - fbeg;
-                const T* sl = lds + slot_offset(frame_pos(f, wave, i), Lp, pad) - d0;  // sl[dd]: displacement dd
+                const T* sl = lds + slot_offset(frame_slot(f, px, pb), Lp, pad) - d0;  // sl[dd]: displacement dd
 #pragma unroll
                 for (int c = 0; c < NCH + 1; ++c) {
                     const int k = 64 * c + lane;

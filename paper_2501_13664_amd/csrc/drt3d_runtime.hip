@@ -547,6 +547,7 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
         L.bytes = bytes;
         if (s0->kind == S_DRT && prog.drt[L.first].fused_group) {
             L.adj_group = 1;
+            L.fast_kx = L.fast_ky = prog.drt[L.first].Kx;  // the fused kernel's K
             L.fast_nch = prog.drt[L.first].L >> 6;
         } else if (s0->kind == S_DRT && (L.block == 512 || L.block == 1024)) {
             // one shape across the launch's descriptors -> specialised kernel
@@ -643,8 +644,8 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
                 return fail(DRT3D_EINVAL, "%s needs %zu bytes of LDS, the device allows %d", L.name.c_str(), L.lds,
                             di.max_lds);
             if (L.adj_group)
-                e = launch_drt_adj_group(p.is_float, L.fast_nch, d_drt + L.first, L.ndesc, L.total_wg,
-                                         grid_for(L.total_wg, di, L.persistent), L.lds, s);
+                e = launch_drt_adj_group(p.is_float, L.fast_kx, L.fast_nch, L.block / 64, d_drt + L.first, L.ndesc,
+                                         L.total_wg, grid_for(L.total_wg, di, L.persistent), L.lds, s);
             else if (L.fast_kx >= 0)
                 e = launch_drt_fast(p.is_float, L.fast_kx, L.fast_ky, L.fast_nch, L.fast_mode, L.block / 64, d_drt + L.first, L.ndesc,
                                     L.total_wg, grid_for(L.total_wg, di, L.persistent), L.lds, s, L.fast_sb, L.fast_db);
@@ -836,19 +837,25 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
     if (runs4 && chunk >= 4 && !adjoint) chunk -= chunk % 4;
     // The adjoint's last pass (the forward's first, transposed) adds the
     // dodecants of each volume layout group into one volume. When every group
-    // present is whole in a single chunk and that pass is a 3.3 pass of eight
-    // wavefronts, one fused launch sums each group's four dodecants per block
-    // (slots in group order); otherwise it runs in rounds, one dodecant of
+    // present is whole in a single chunk and that pass is square (2.2 or 3.3,
+    // eight wavefronts, or sixteen for 3.3), one fused launch sums each
+    // group's four dodecants per block (slots in group order); otherwise it runs in rounds, one dodecant of
     // each group per round, and mixing the groups inside a chunk makes fewer,
     // fuller rounds.
     bool fuse_last = false;
+    int fuse_waves = 8;
     if (adjoint) {
         const PassGeom& g0 = P[0];
         int T0, H0, L0, nt0;
-        const int w0 = std::min(t.waves, std::max(1, 1 << (g0.Kx + g0.Ky - 1)));
-        fuse_last = runs4 && chunk == nd && g0.Kx == 3 && g0.Ky == 3 && w0 == 8 &&
-                    choose_tiles(g0, 1, t.lds_elems, T0, H0, L0, nt0) && (L0 & 63) == 0 && (L0 >> 6) <= 4 &&
-                    drt_adj_group_kernel(is_float, L0 >> 6) != nullptr;  // wider tiles would spill its sums
+        int w0 = std::min(t.waves, std::max(1, 1 << (g0.Kx + g0.Ky - 1)));
+        if (w0 > 8 && !(g0.Kx == 3 && g0.Ky == 3)) w0 = 8;
+        // 3.3 with eight wavefronts keeps 8 columns per wave in registers: up
+        // to 4 chunks fit without spilling its sums
+        const int max_nch = g0.Kx == 3 && w0 == 8 ? 4 : 6;
+        fuse_last = runs4 && chunk == nd && g0.Kx == g0.Ky && (g0.Kx == 2 || g0.Kx == 3) && (w0 == 8 || w0 == 16) &&
+                    choose_tiles(g0, 1, t.lds_elems, T0, H0, L0, nt0) && (L0 & 63) == 0 && (L0 >> 6) <= max_nch &&
+                    drt_adj_group_kernel(is_float, g0.Kx, L0 >> 6, w0) != nullptr;
+        fuse_waves = w0;
         if (!fuse_last) {
             int by[3][4], c[3] = {0, 0, 0}, q = 0;
             for (int i = 0; i < nd; ++i) { const int g = drt_group(dods[i]); by[g][c[g]++] = dods[i]; }
@@ -954,7 +961,7 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             if (last && adjoint && fuse_last) {
                 d.fused_group = 1;
                 Step s; s.kind = S_DRT; s.key = kKeyRound; s.name = nm;
-                s.waves = 8; s.lds = lds; s.shape = shape | (1 << 24);
+                s.waves = fuse_waves; s.lds = lds; s.shape = shape | (1 << 24);
                 s.bytes = cols * elem * ((double)ns * d.E_in + (double)(ns / 4) * d.E_out);
                 s.drt.push_back(d);
                 steps.push_back(s);
@@ -2056,8 +2063,14 @@ int drt3d_plan_text(int op, int N, uint32_t mask, int dtype, char* buf, size_t c
     std::string txt;
     char line[256];
     for (const Launch& L : prog.launches) {
-        snprintf(line, sizeof line, "%s kind=%d wg=%lld block=%d lds=%zu bytes=%.0f\n", L.name.c_str(), L.kind,
-                 L.total_wg, L.block, L.lds, L.bytes);
+        // which DRT pass kernel runs: the fused adjoint group pass, a
+        // shape-specialised pass (K1.K2 x wavefronts), or the generic one
+        char kern[32] = "-";
+        if (L.kind == S_DRT)
+            snprintf(kern, sizeof kern, L.adj_group ? "group%d.%dx%d" : L.fast_kx >= 0 ? "fast%d.%dx%d" : "generic",
+                     L.fast_kx, L.fast_ky, L.block / 64);
+        snprintf(line, sizeof line, "%s kind=%d wg=%lld block=%d lds=%zu bytes=%.0f kernel=%s\n", L.name.c_str(),
+                 L.kind, L.total_wg, L.block, L.lds, L.bytes, kern);
         txt += line;
     }
     if (buf && cap) {

@@ -176,9 +176,16 @@ def test_plan_text_lists_the_launches():
     text = buf.value.decode()
     assert n == len(text.strip().splitlines())
     assert text.count("transpose_in") == 2 and "drt_fwd_p" in text
+    assert all(l.split("kernel=")[1].startswith("fast") for l in text.splitlines() if "kind=0" in l)
     n = L.drt3d_plan_text(1, 64, 0x00F, 1, buf, len(buf))
     text = buf.value.decode()
     assert "drt_adj" in text and "transpose_out" not in text  # z-normal dodecants only
+    # all twelve dodecants: the adjoint's last pass sums each layout group's
+    # four dodecants in one fused launch
+    for N, dt, kern in ((512, 0, "group3.3x8"), (512, 1, "group3.3x16"), (128, 0, "group2.2x8")):
+        L.drt3d_plan_text(1, N, 0xFFF, dt, buf, len(buf))
+        last = [l for l in buf.value.decode().splitlines() if "kind=0" in l][-1]
+        assert last.startswith("drt_adj_p1 ") and last.endswith("kernel=" + kern), (N, dt, last)
     n = L.drt3d_plan_text(2, 16, 0xFFF, 0, buf, len(buf))
     assert n == 2 and buf.value.decode().count("djt_p") == 2  # 4 stages fused 2 + 2
     # the DJT adjoint: the same passes transposed, last first, then the sum of
