@@ -7,3 +7,4 @@ it, and the two share no code.
 from .oracle import *  # noqa: F401,F403
 from .inverse import *  # noqa: F401,F403
 from .net import *  # noqa: F401,F403
+from .planes import *  # noqa: F401,F403

@@ -2,7 +2,7 @@
 
 This module holds none of the transforms' arithmetic: it only draws cubes with
 numpy's PCG64 generator. The shapes and value distributions stand in for the
-paper's workloads (a voxelized depth scene with planes, Sec. 6.2; a ray buried
+paper's workloads (a voxelized depth scene with planes, Sec. 6.1; a ray buried
 in noise, Sec. 4.1; corner voxels and the centre of a cube, Sec. 5.1), whose data
 are not available. Planes and segments are drawn as rounded continuous planes
 and lines, not as the transforms' own digital sets.
@@ -14,7 +14,7 @@ import numpy as np
 __all__ = [
     "uniform_int_cube", "normal_cube", "point_cloud_with_planes",
     "noise_with_segments", "mixed_batch", "corners_and_centre", "normal_batch",
-    "normal_weights", "random_voxels", "WORKLOADS",
+    "normal_weights", "random_voxels", "room_scene", "WORKLOADS",
 ]
 
 
@@ -129,6 +129,62 @@ def corners_and_centre(N: int = 64, value: int = 1) -> np.ndarray:
                 vol[x, y, z] = value
     vol[N // 2, N // 2, N // 2] = value
     return vol
+
+
+def _sample_rect(origin, du, dv, h=0.5):
+    """Points of the parallelogram origin + a du + b dv, a, b in [0, 1], on a
+    grid of step h voxels along each edge."""
+    origin, du, dv = (np.asarray(v, dtype=np.float64) for v in (origin, du, dv))
+    na = max(2, int(np.ceil(np.linalg.norm(du) / h)) + 1)
+    nb = max(2, int(np.ceil(np.linalg.norm(dv) / h)) + 1)
+    a, b = np.meshgrid(np.linspace(0, 1, na), np.linspace(0, 1, nb), indexing="ij")
+    return origin + a.reshape(-1, 1) * du + b.reshape(-1, 1) * dv
+
+
+def room_scene(N: int = 128, seed: int = 11, n_objects: int = 6, noise: float = 0.002):
+    """A voxelized indoor depth scene (the plane-detection example of Sec. 6.1),
+    as an int32 occupancy cube (1 = a surface point was seen there).
+
+    A box-shaped room turned by a random yaw about the vertical z axis, seen
+    from inside: the floor, the half of the ceiling away from the sensor and
+    three walls (the fourth is behind the sensor), sampled every half voxel and
+    rounded to voxels; boxes standing on the floor (top and four sides); and a
+    fraction ``noise`` of the voxels set at random. Returns (cube, surfaces)
+    where surfaces maps "floor", "ceiling", "back", "left", "right" to the unit
+    normal (x, y, z) of that surface."""
+    rng = _rng(seed)
+    yaw = np.deg2rad(rng.uniform(8.0, 25.0))
+    cu, su = np.cos(yaw), np.sin(yaw)
+    U = np.array([cu, su, 0.0])   # the room's depth axis (towards the back wall)
+    V = np.array([-su, cu, 0.0])  # its width axis
+    Z = np.array([0.0, 0.0, 1.0])
+    c = np.array([N / 2.0, N / 2.0, 0.0])
+    au, av = 0.40 * N, 0.38 * N          # half depth and half width
+    z0, z1 = 0.10 * N, 0.88 * N          # floor and ceiling heights
+    corner = lambda u, v, z: c + u * U + v * V + z * Z
+    pts = [
+        _sample_rect(corner(-au, -av, z0), 2 * au * U, 2 * av * V),            # floor
+        _sample_rect(corner(0.0, -av, z1), au * U, 2 * av * V),                 # ceiling, far half
+        _sample_rect(corner(au, -av, z0), 2 * av * V, (z1 - z0) * Z),          # back wall
+        _sample_rect(corner(-au, -av, z0), 2 * au * U, (z1 - z0) * Z),         # left wall
+        _sample_rect(corner(-au, av, z0), 2 * au * U, (z1 - z0) * Z),          # right wall
+    ]
+    for _ in range(n_objects):
+        u0, v0 = rng.uniform(-0.6 * au, 0.6 * au), rng.uniform(-0.6 * av, 0.6 * av)
+        wu, wv = rng.uniform(0.05, 0.15, size=2) * N
+        hz = rng.uniform(0.05, 0.25) * N
+        b = corner(u0, v0, z0)
+        pts.append(_sample_rect(b + hz * Z, wu * U, wv * V))                    # top
+        for o, d in ((b, wu * U), (b, wv * V), (b + wv * V, wu * U), (b + wu * U, wv * V)):
+            pts.append(_sample_rect(o, d, hz * Z))                              # sides
+    p = np.rint(np.concatenate(pts)).astype(np.int64)
+    p = p[np.all((p >= 0) & (p < N), axis=1)]
+    vol = np.zeros((N, N, N), dtype=np.int32)
+    vol[p[:, 0], p[:, 1], p[:, 2]] = 1
+    count = int(round(noise * N ** 3))
+    vol.reshape(-1)[rng.choice(N ** 3, size=count, replace=False)] = 1
+    surfaces = {"floor": Z, "ceiling": -Z, "back": -U, "left": V, "right": -V}
+    return vol, surfaces
 
 
 # Named workloads with the sizes they are quoted at.
