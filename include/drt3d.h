@@ -159,6 +159,43 @@ size_t drt3d_net_elems(int N);
  * claimed to be continuous across block edges. */
 int drt3d_merge_net(const void* proj, void* net, int N, int dtype, void* stream);
 
+/* ---- plane detection (Sec. 6.1) ------------------------------------------------ */
+/* The application of Sec. 6.1 on a DRT output proj ([count][N][N][3N-2] in the
+ * drt3d_forward layout of mask, int32 or float32, device memory):
+ *   1. the dominant plane is the largest bin (ties: the smallest flat index;
+ *      int32 compares as signed; NaN inputs are not supported);
+ *   2. a bin (j, s1, s2, dd) qualifies when its plane is orthogonal to the
+ *      dominant one, |cos| <= cos_tol between the integer normals of
+ *      drt3d_plane_normal, decided as (a.b)^2 <= cos_tol^2 |a|^2 |b|^2 in
+ *      float64; it is a relative maximum of its dodecant's output: over the
+ *      26 neighbours (s1+a, s2+b, dd+c) that exist, those earlier in the layout
+ *      are strictly below it and those later are not above it; and its value is
+ *      >= rel_threshold x the dominant value, in float64.
+ * bins (device, cap >= 1 entries of int64): bins[0] = the dominant bin's flat
+ * index, then the qualifying bins' flat indices in ascending order, as many as
+ * fit. count (device, one int64) = 1 + the number of qualifying bins, which may
+ * exceed cap. cos_tol in [0, 1). Stream-ordered, no host synchronisation.
+ * Workspace: drt3d_detect_planes_workspace_bytes(N, mask, dtype), 256-byte
+ * aligned (about 12 bytes per output column). */
+size_t drt3d_detect_planes_workspace_bytes(int N, uint32_t mask, int dtype);
+int drt3d_detect_planes(const void* proj, int N, uint32_t mask, int dtype, double cos_tol, double rel_threshold,
+                        long long* bins, long long cap, long long* count, void* workspace, size_t workspace_bytes,
+                        void* stream);
+/* vol_out ([N][N][N], dtype, overwritten) = the adjoint (drt3d_adjoint) of the
+ * projection holding 1 at each of the first min(count[0], cap) flat indices of
+ * bins (device memory, as drt3d_detect_planes writes them) and 0 elsewhere:
+ * per voxel, the number of listed planes through it. Indices outside the
+ * output are skipped. Workspace: drt3d_backproject_bins_workspace_bytes
+ * (a 0/1 projection of 4 bytes per bin plus the adjoint's workspace). */
+size_t drt3d_backproject_bins_workspace_bytes(int N, uint32_t mask, int dtype);
+int drt3d_backproject_bins(const long long* bins, const long long* count, long long cap, void* vol_out, int N,
+                           uint32_t mask, int dtype, void* workspace, size_t workspace_bytes, void* stream);
+/* Integer normal (x, y, z) of dodecant k's planes at slopes (s1, s2), scaled by
+ * N-1: in the dodecant's frame the planes z' = s1 x'/(N-1) + s2 y'/(N-1) + d
+ * (up to the discrete lines) have the normal (-s1, -s2, N-1) (Sec. 3); the
+ * frame table of drt3d_frame_map carries it to the original axes. Host only. */
+int drt3d_plane_normal(int k, int s1, int s2, int N, int out[3]);
+
 /* ---- inverse ---------------------------------------------------------------- */
 /* Iterative inverse of the 12-dodecant DRT (Sec. 5.2), float32 only: given
  * proj = drt3d_forward(f) for all 12 dodecants ([12][N][N][3N-2] float32),

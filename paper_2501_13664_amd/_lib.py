@@ -44,6 +44,12 @@ SIGNATURES = {
     "djt3d_adjoint_batched": (_int, [_int, _ptrs, _ptrs, _ints, _u32, _int, _vp, _sz, _vp]),
     "drt3d_net_elems": (_sz, [_int]),
     "drt3d_merge_net": (_int, [_vp, _vp, _int, _int, _vp]),
+    "drt3d_detect_planes_workspace_bytes": (_sz, [_int, _u32, _int]),
+    "drt3d_detect_planes": (_int, [_vp, _int, _u32, _int, ctypes.c_double, ctypes.c_double, _vp, ctypes.c_longlong,
+                                   _vp, _vp, _sz, _vp]),
+    "drt3d_backproject_bins_workspace_bytes": (_sz, [_int, _u32, _int]),
+    "drt3d_backproject_bins": (_int, [_vp, _vp, ctypes.c_longlong, _vp, _int, _u32, _int, _vp, _sz, _vp]),
+    "drt3d_plane_normal": (_int, [_int, _int, _int, _int, _ints]),
     "drt3d_inverse_workspace_bytes": (_sz, [_int]),
     "drt3d_inverse": (_int, [_vp, _vp, _int, _int, ctypes.POINTER(ctypes.c_double), _vp, _sz, _vp]),
     "drt3d_inverse_lambdas": (_int, [_int, ctypes.POINTER(ctypes.c_double), _vp, _sz, _vp]),

@@ -17,6 +17,7 @@ __all__ = [
     "DRT3D_ALL", "drt3d_forward", "djt3d_forward", "drt3d_adjoint", "djt3d_adjoint",
     "drt3d_forward_batched", "djt3d_forward_batched", "drt3d_adjoint_batched", "djt3d_adjoint_batched",
     "drt3d_inverse", "drt3d_inverse_lambdas", "drt3d_merge_net",
+    "drt3d_detect_planes", "drt3d_backproject_bins", "drt3d_plane_normal",
     "drt3d_out_shape", "djt3d_out_shape", "drt3d_autotune", "drt3d_tuning_string",
     "drt3d_set_tuning", "profile", "dodecant_count",
 ]
@@ -246,6 +247,63 @@ def drt3d_merge_net(proj: torch.Tensor, out: Optional[torch.Tensor] = None, stre
         raise ValueError("out must be a contiguous %s tensor of shape %s" % (proj.dtype, shape))
     check(lib().drt3d_merge_net(_ptr(proj), _ptr(out), N, dt, _stream(stream)))
     return out
+
+
+def _proj_N(proj: torch.Tensor, mask: int) -> int:
+    if proj.dim() != 4:
+        raise ValueError("proj must be [count][N][N][3N-2]")
+    N = int(proj.shape[1])
+    if tuple(proj.shape) != drt3d_out_shape(N, mask) or not proj.is_cuda or not proj.is_contiguous():
+        raise ValueError("proj must be a contiguous device tensor of shape %s" % (drt3d_out_shape(N, mask),))
+    return N
+
+
+def drt3d_detect_planes(proj: torch.Tensor, cos_tol: float = 0.05, rel_threshold: float = 0.5,
+                        mask: int = DRT3D_ALL, cap: int = 4096, workspace: Optional[torch.Tensor] = None,
+                        stream=None):
+    """Plane detection in a DRT output (Sec. 6.1): returns (bins, count), bins
+    an int64 device tensor of flat output indices (the dominant plane first,
+    then the qualifying planes in ascending order, at most cap of them) and
+    count the number found (which may exceed cap). Reads count back, so the
+    call waits for the stream."""
+    N = _proj_N(proj, mask)
+    dt = _dtype_code(proj)
+    ws = _workspace(lib().drt3d_detect_planes_workspace_bytes(N, mask, dt), proj.device, workspace)
+    bins = torch.empty(max(1, int(cap)), dtype=torch.int64, device=proj.device)
+    count = torch.empty(1, dtype=torch.int64, device=proj.device)
+    check(lib().drt3d_detect_planes(_ptr(proj), N, mask, dt, float(cos_tol), float(rel_threshold), _ptr(bins),
+                                    bins.numel(), _ptr(count), _ptr(ws), ws.numel() * ws.element_size(),
+                                    _stream(stream)))
+    n = int(count.item())
+    return bins[:min(n, bins.numel())], n
+
+
+def drt3d_backproject_bins(bins: torch.Tensor, N: int, mask: int = DRT3D_ALL, dtype=torch.int32,
+                           out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                           stream=None) -> torch.Tensor:
+    """Per voxel, the number of listed planes through it: the adjoint of the
+    0/1 projection marking the flat indices in bins (int64 device tensor)."""
+    if bins.dtype != torch.int64 or not bins.is_cuda or bins.dim() != 1 or not bins.is_contiguous():
+        raise ValueError("bins must be a contiguous 1-D int64 device tensor")
+    dt = DRT3D_F32 if dtype == torch.float32 else DRT3D_I32
+    if out is None:
+        out = torch.empty((N, N, N), dtype=dtype, device=bins.device)
+    elif tuple(out.shape) != (N, N, N) or out.dtype != dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous %s tensor of shape %s" % (dtype, (N, N, N)))
+    ws = _workspace(lib().drt3d_backproject_bins_workspace_bytes(N, mask, dt), bins.device, workspace)
+    count = torch.full((1,), bins.numel(), dtype=torch.int64, device=bins.device)
+    if bins.numel() == 0:  # no planes: a valid pointer, nothing read
+        bins = torch.zeros(1, dtype=torch.int64, device=bins.device)
+    check(lib().drt3d_backproject_bins(_ptr(bins), _ptr(count), bins.numel(), _ptr(out), N, mask, dt,
+                                       _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    return out
+
+
+def drt3d_plane_normal(k: int, s1: int, s2: int, N: int):
+    """Integer normal (x, y, z) of dodecant k's planes at slopes (s1, s2), scaled by N-1."""
+    arr = (ctypes.c_int * 3)()
+    check(lib().drt3d_plane_normal(k, s1, s2, N, arr))
+    return tuple(arr)
 
 
 def _inverse_workspace(N: int, device, workspace):

@@ -157,4 +157,24 @@ hipError_t launch_normalize(const float* w, float* v, long long n, double* scrat
 // Algorithm 2's merged 4N x 4N x (3N-2) net from the 12-dodecant output.
 hipError_t launch_merge_net(int is_float, const void* R, void* net, int N, hipStream_t s);
 
+// Plane detection (Sec. 6.1). For the output's dodecant rank j, ks[j] is the
+// dodecant; for dodecant k and original axis i (x, y, z), axis[k][i] is the
+// primed axis that runs along it and sign[k][i] is -1 where it is mirrored.
+struct PlaneFrames {
+    int ks[12];
+    signed char axis[12][3];
+    signed char sign[12][3];
+};
+int argmax_parts(long long n);
+// pv[nparts] (4-byte values), pi[nparts]: partials; top[0] = the largest
+// element's index (ties: the smallest), thr[0] = rel * its value, bins[0] = top
+hipError_t launch_argmax(int is_float, const void* p, long long n, void* pv, long long* pi, int nparts, double rel,
+                         long long* top, double* thr, long long* bins, hipStream_t s);
+hipError_t launch_plane_peaks(int is_float, int write, const void* p, int N, int nk, const PlaneFrames& F,
+                              const long long* top, const double* thr, double tol2, int* counts,
+                              const long long* offsets, long long* bins, long long cap, hipStream_t s);
+hipError_t launch_peak_scan(const int* counts, long long m, long long* offsets, long long* count, hipStream_t s);
+hipError_t launch_scatter_ones(const long long* bins, const long long* count, long long cap, uint32_t* marker,
+                               long long n, uint32_t one, hipStream_t s);
+
 }  // namespace drt3d

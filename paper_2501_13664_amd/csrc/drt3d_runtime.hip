@@ -1552,6 +1552,122 @@ int drt3d_merge_net(const void* proj, void* net, int N, int dtype, void* stream)
     return DRT3D_OK;
 }
 
+// ------------------------------------------------------------------ plane detection ABI
+// The application of Sec. 6.1 on the DRT output: the dominant plane (largest
+// bin), then the bins orthogonal to it that are relative maxima and reach a
+// threshold; backprojection of listed bins through the adjoint.
+namespace {
+struct DetectLayout {
+    size_t pv = 0, pi = 0, top = 0, thr = 0, counts = 0, offsets = 0, total = 0;
+};
+void detect_layout(int N, uint32_t mask, DetectLayout& L)
+{
+    const long long n = (long long)popcount12(mask) * N * N * (3 * N - 2);
+    const long long ncol = (long long)popcount12(mask) * N * N;
+    const int parts = argmax_parts(n);
+    size_t o = 0;
+    L.pv = o; o = align256(o + 4 * (size_t)parts);
+    L.pi = o; o = align256(o + 8 * (size_t)parts);
+    L.top = o; o = align256(o + 8);
+    L.thr = o; o = align256(o + 8);
+    L.counts = o; o = align256(o + 4 * (size_t)ncol);
+    L.offsets = o; o = align256(o + 8 * (size_t)ncol);
+    L.total = o;
+}
+void plane_frames(uint32_t mask, PlaneFrames& F)
+{
+    F = PlaneFrames{};
+    int j = 0;
+    for (int k = 0; k < 12; ++k) {
+        if ((mask >> k) & 1) F.ks[j++] = k;
+        AxisMap ax[3];
+        frame_axes(k, ax);
+        for (int i = 0; i < 3; ++i) {
+            F.axis[k][i] = (signed char)ax[i].primed;
+            F.sign[k][i] = (signed char)(ax[i].mirror ? -1 : 1);
+        }
+    }
+}
+}  // namespace
+
+size_t drt3d_detect_planes_workspace_bytes(int N, uint32_t mask, int dtype)
+{
+    if (check_common(N, mask, dtype) != DRT3D_OK) return 0;
+    DetectLayout L;
+    detect_layout(N, mask, L);
+    return L.total;
+}
+
+int drt3d_detect_planes(const void* proj, int N, uint32_t mask, int dtype, double cos_tol, double rel_threshold,
+                        long long* bins, long long cap, long long* count, void* workspace, size_t workspace_bytes,
+                        void* stream)
+{
+    TRY(check_common(N, mask, dtype));
+    TRY(check_ptr(proj, "proj"));
+    if (!bins || ((uintptr_t)bins & 7)) return fail(DRT3D_EINVAL, "bins is NULL or not 8-byte aligned");
+    if (!count || ((uintptr_t)count & 7)) return fail(DRT3D_EINVAL, "count is NULL or not 8-byte aligned");
+    if (cap < 1) return fail(DRT3D_EINVAL, "cap must be at least 1, got %lld", cap);
+    if (!(cos_tol >= 0.0 && cos_tol < 1.0)) return fail(DRT3D_EINVAL, "cos_tol must lie in [0, 1), got %g", cos_tol);
+    if (!std::isfinite(rel_threshold)) return fail(DRT3D_EINVAL, "rel_threshold must be finite");
+    DetectLayout L;
+    detect_layout(N, mask, L);
+    TRY(check_ws(workspace, workspace_bytes, L.total));
+    char* w = (char*)workspace;
+    const hipStream_t s = (hipStream_t)stream;
+    const int is_float = dtype == DRT3D_F32;
+    const int nk = popcount12(mask);
+    const long long n = (long long)nk * N * N * (3 * N - 2), ncol = (long long)nk * N * N;
+    const int parts = argmax_parts(n);
+    long long* top = (long long*)(w + L.top);
+    double* thr = (double*)(w + L.thr);
+    int* counts = (int*)(w + L.counts);
+    long long* offsets = (long long*)(w + L.offsets);
+    PlaneFrames F;
+    plane_frames(mask, F);
+    const double tol2 = cos_tol * cos_tol;
+    HIP_TRY(launch_argmax(is_float, proj, n, w + L.pv, (long long*)(w + L.pi), parts, rel_threshold, top, thr, bins, s));
+    HIP_TRY(launch_plane_peaks(is_float, 0, proj, N, nk, F, top, thr, tol2, counts, offsets, bins, cap, s));
+    HIP_TRY(launch_peak_scan(counts, ncol, offsets, count, s));
+    HIP_TRY(launch_plane_peaks(is_float, 1, proj, N, nk, F, top, thr, tol2, counts, offsets, bins, cap, s));
+    return DRT3D_OK;
+}
+
+size_t drt3d_backproject_bins_workspace_bytes(int N, uint32_t mask, int dtype)
+{
+    if (check_common(N, mask, dtype) != DRT3D_OK) return 0;
+    return align256(drt3d_out_elems(N, mask) * 4) + drt3d_adjoint_workspace_bytes(N, mask, dtype);
+}
+
+int drt3d_backproject_bins(const long long* bins, const long long* count, long long cap, void* vol_out, int N,
+                           uint32_t mask, int dtype, void* workspace, size_t workspace_bytes, void* stream)
+{
+    TRY(check_common(N, mask, dtype));
+    if (!bins || ((uintptr_t)bins & 7)) return fail(DRT3D_EINVAL, "bins is NULL or not 8-byte aligned");
+    if (!count || ((uintptr_t)count & 7)) return fail(DRT3D_EINVAL, "count is NULL or not 8-byte aligned");
+    if (cap < 0) return fail(DRT3D_EINVAL, "cap must not be negative, got %lld", cap);
+    TRY(check_ptr(vol_out, "vol_out"));
+    TRY(check_ws(workspace, workspace_bytes, drt3d_backproject_bins_workspace_bytes(N, mask, dtype)));
+    const long long n = (long long)drt3d_out_elems(N, mask);
+    const size_t mbytes = align256((size_t)n * 4);
+    uint32_t* marker = (uint32_t*)workspace;
+    const hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_fill((float*)marker, 0.f, n, s));
+    if (cap > 0)
+        HIP_TRY(launch_scatter_ones(bins, count, cap, marker, n, dtype == DRT3D_F32 ? 0x3f800000u : 1u, s));
+    return drt_single(marker, vol_out, N, mask, dtype, (char*)workspace + mbytes, workspace_bytes - mbytes, stream, 1);
+}
+
+int drt3d_plane_normal(int k, int s1, int s2, int N, int out[3])
+{
+    if (k < 0 || k > 11 || ilog2_exact(N) < 1 || s1 < 0 || s1 >= N || s2 < 0 || s2 >= N || !out)
+        return fail(DRT3D_EINVAL, "bad arguments to drt3d_plane_normal");
+    AxisMap ax[3];
+    frame_axes(k, ax);
+    const int c[3] = {-s1, -s2, N - 1};
+    for (int i = 0; i < 3; ++i) out[i] = (ax[i].mirror ? -1 : 1) * c[ax[i].primed];
+    return DRT3D_OK;
+}
+
 // ------------------------------------------------------------------ inverse ABI
 // Iterative inverse of the 12-dodecant DRT (Sec. 5.2): Press's iterative
 // improvement with the approximate inverse H A^T (H the printed 3x3x3

@@ -222,3 +222,51 @@ def test_frame_maps_agree_with_the_oracle(oracle_mod, kind):
             a, b, c = (p[0], p[1], N - 1 - p[2]) if kind == 0 else (N - 1 - p[0], N - 1 - p[1], p[2])
             assert base + sx * a + sy * b + sd * c == layouts[group](x, y, z), (k, tuple(p))
     assert L.drt3d_frame_map(12, N, 0, out) == EINVAL
+
+
+def test_plane_normals_agree_with_the_oracle(oracle_mod):
+    """The library's plane normals (host code) against the oracle's, every
+    dodecant, a spread of slopes and sizes."""
+    from oracle.planes import plane_normal
+    L = _lib()
+    out = (ctypes.c_int * 3)()
+    for N in (2, 8, 64, 512):
+        for k in range(12):
+            for s1, s2 in ((0, 0), (N - 1, 0), (0, N - 1), (N // 2, N - 1), (1, N // 2)):
+                assert L.drt3d_plane_normal(k, s1, s2, N, out) == OK
+                assert list(out) == plane_normal(k, s1, s2, N).tolist(), (N, k, s1, s2)
+    for args in ((12, 0, 0, 8), (0, 8, 0, 8), (0, 0, -1, 8), (0, 0, 0, 6)):
+        assert L.drt3d_plane_normal(*args, out) == EINVAL
+
+
+def test_plane_detection_argument_checks():
+    """Detection and backprojection validate sizes, pointers, tolerances and
+    workspace before any device work."""
+    L = _lib()
+    A = _fake(1 << 20)
+    need = L.drt3d_detect_planes_workspace_bytes(8, 0xFFF, 0)
+    # partials, top, threshold, then 4 + 8 bytes per output column
+    assert need >= 12 * 12 * 8 * 8 and L.drt3d_detect_planes_workspace_bytes(16, 0xFFF, 1) > need
+    assert L.drt3d_detect_planes_workspace_bytes(6, 0xFFF, 0) == 0
+    assert L.drt3d_detect_planes_workspace_bytes(8, 0xFFF, 2) == 0  # int32 and float32 only
+    bneed = L.drt3d_backproject_bins_workspace_bytes(8, 0xFFF, 0)
+    assert bneed >= 12 * 8 * 8 * 22 * 4 + L.drt3d_adjoint_workspace_bytes(8, 0xFFF, 0)
+    cases = [
+        (lambda: L.drt3d_detect_planes(A, 6, 0xFFF, 0, 0.05, 0.5, A, 16, A, A, need, None), EINVAL, "power of two"),
+        (lambda: L.drt3d_detect_planes(None, 8, 0xFFF, 0, 0.05, 0.5, A, 16, A, A, need, None), EINVAL, "NULL"),
+        (lambda: L.drt3d_detect_planes(A, 8, 0xFFF, 0, 0.05, 0.5, None, 16, A, A, need, None), EINVAL, "bins"),
+        (lambda: L.drt3d_detect_planes(A, 8, 0xFFF, 0, 0.05, 0.5, A, 0, A, A, need, None), EINVAL, "cap"),
+        (lambda: L.drt3d_detect_planes(A, 8, 0xFFF, 0, 0.05, 0.5, A, 16, None, A, need, None), EINVAL, "count"),
+        (lambda: L.drt3d_detect_planes(A, 8, 0xFFF, 0, 1.0, 0.5, A, 16, A, A, need, None), EINVAL, "cos_tol"),
+        (lambda: L.drt3d_detect_planes(A, 8, 0xFFF, 0, -0.1, 0.5, A, 16, A, A, need, None), EINVAL, "cos_tol"),
+        (lambda: L.drt3d_detect_planes(A, 8, 0xFFF, 0, 0.05, float("nan"), A, 16, A, A, need, None), EINVAL,
+         "rel_threshold"),
+        (lambda: L.drt3d_detect_planes(A, 8, 0xFFF, 0, 0.05, 0.5, A, 16, A, A, need - 1, None), ENOMEM, "smaller"),
+        (lambda: L.drt3d_backproject_bins(A, A, 4, A, 8, 0xFFF, 0, A, bneed - 1, None), ENOMEM, "smaller"),
+        (lambda: L.drt3d_backproject_bins(None, A, 4, A, 8, 0xFFF, 0, A, bneed, None), EINVAL, "bins"),
+        (lambda: L.drt3d_backproject_bins(A, A, -1, A, 8, 0xFFF, 0, A, bneed, None), EINVAL, "cap"),
+        (lambda: L.drt3d_backproject_bins(A, A, 4, None, 8, 0xFFF, 0, A, bneed, None), EINVAL, "NULL"),
+    ]
+    for fn, code, word in cases:
+        assert fn() == code
+        assert word in L.drt3d_last_error().decode()

@@ -14,7 +14,7 @@ import numpy as np
 __all__ = [
     "uniform_int_cube", "normal_cube", "point_cloud_with_planes",
     "noise_with_segments", "mixed_batch", "corners_and_centre", "normal_batch",
-    "normal_weights", "random_voxels", "room_scene", "WORKLOADS",
+    "normal_weights", "random_voxels", "room_scene", "random_projection", "WORKLOADS",
 ]
 
 
@@ -185,6 +185,17 @@ def room_scene(N: int = 128, seed: int = 11, n_objects: int = 6, noise: float = 
     vol.reshape(-1)[rng.choice(N ** 3, size=count, replace=False)] = 1
     surfaces = {"floor": Z, "ceiling": -Z, "back": -U, "left": V, "right": -V}
     return vol, surfaces
+
+
+def random_projection(N: int, count: int = 12, seed: int = 21, dtype=np.int32, levels: int = 16) -> np.ndarray:
+    """A DRT-output-shaped array [count][N][N][3N-2] of seeded values with many
+    ties: integers in [0, levels) (int32), or N(0,1) rounded to eighths
+    (float32). Stands in for a transform output where only its shape matters."""
+    rng = _rng(seed)
+    shape = (count, N, N, 3 * N - 2)
+    if np.dtype(dtype) == np.float32:
+        return (np.round(rng.standard_normal(size=shape) * 8) / 8).astype(np.float32)
+    return rng.integers(0, levels, size=shape).astype(np.int32)
 
 
 # Named workloads with the sizes they are quoted at.
