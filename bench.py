@@ -23,9 +23,11 @@ autograd) of a batch of 8 float32 N=128 cubes against per-volume forward +
 adjoint calls (both check that the two ways give bit-identical results); the
 3D DJT of one N=128 int32 cube, with U = 12 * 8 N^3 (N-1) voxel-stage updates,
 and its adjoint; Algorithm 2's merged net of the projections and the same cube's
-forward as uint8 with narrow storage (both with the adjoint); and the
-iterative inverse of a float32 N=128 DRT (ten
-V-cycles) with its error after each cycle count.
+forward as uint8 with narrow storage (both with the adjoint); the
+iterative inverse of a float32 N=128 DRT (ten V-cycles) with its error after
+each cycle count; and plane detection (Sec. 6.1, --no-planes): on the
+benchmark's projections, and end to end (forward, detection, backprojection)
+on an N=128 voxelized room scene.
 
 --copy-calibration runs only a plain 1 GiB device-to-device copy (five times),
 the reference kernel that scales the HBM byte counters.
@@ -268,6 +270,48 @@ def merge_net_rate(api, torch, proj, reps=3):
             "bytes": nbytes, "GBps": nbytes / (ms / 1e3) / 1e9, "frac_of_hbm_peak": nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
 
 
+def planes_rate(api, torch, proj, reps=3):
+    """Plane detection (Sec. 6.1): on the benchmark's N=512 projections (the
+    maximum reads all 19.3 GB once; the peak search reads the columns
+    orthogonal to the dominant plane), and the whole application on a
+    voxelized N=128 room scene: forward, detection, backprojection of the
+    detected planes, in frames per second."""
+    import workloads
+    N = int(proj.shape[1])
+    from paper_2501_13664_amd._lib import lib
+    ws = torch.empty(lib().drt3d_detect_planes_workspace_bytes(N, 0xFFF, 0), dtype=torch.uint8, device="cuda")
+    found = {}
+
+    def det():
+        found["r"] = api.drt3d_detect_planes(proj, 0.05, 0.5, cap=1 << 16, workspace=ws)
+
+    ms = _best_ms(torch, det, reps)
+    nbytes = 4.0 * proj.numel()
+    res = {"workload": "drt3d_detect_planes N=%d int32 (the forward's projections), cos_tol 0.05, threshold 0.5" % N,
+           "ms": ms, "planes": found["r"][1], "output_GBps": nbytes / (ms / 1e3) / 1e9}
+    Nr = 128
+    vol, _ = workloads.room_scene(Nr)
+    v = torch.from_numpy(vol).cuda()
+    pr = torch.empty(api.drt3d_out_shape(Nr), dtype=torch.int32, device="cuda")
+    fws = torch.empty(lib().drt3d_workspace_bytes(Nr, 0xFFF, 0), dtype=torch.uint8, device="cuda")
+    dws = torch.empty(lib().drt3d_detect_planes_workspace_bytes(Nr, 0xFFF, 0), dtype=torch.uint8, device="cuda")
+    bws = torch.empty(lib().drt3d_backproject_bins_workspace_bytes(Nr, 0xFFF, 0), dtype=torch.uint8, device="cuda")
+    back = torch.empty((Nr, Nr, Nr), dtype=torch.int32, device="cuda")
+
+    def scene():
+        api.drt3d_forward(v, out=pr, workspace=fws)
+        b, n = api.drt3d_detect_planes(pr, 0.05, 0.5, cap=4096, workspace=dws)
+        api.drt3d_backproject_bins(b, Nr, out=back, workspace=bws)
+        found["scene"] = n
+
+    sms = _best_ms(torch, scene, reps + 2)
+    marked = int(((back > 0) & (v > 0)).sum())
+    res["room_scene"] = {"workload": "room scene N=128 (seed 11): forward + detection + backprojection",
+                         "ms": sms, "frames_per_s": 1e3 / sms, "planes": found["scene"],
+                         "occupied_voxels_on_detected_planes": marked / int(v.sum())}
+    return res
+
+
 def inverse_rate(api, torch, N=128, cycles=10, reps=2):
     """The iterative inverse (Sec. 5.2) of the 12-dodecant float32 DRT of the
     corners-and-centre cube (value 1 on the 8 corners and the centre voxel) at
@@ -323,6 +367,7 @@ def main():
     ap.add_argument("--no-djt", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-inverse", action="store_true")
+    ap.add_argument("--no-planes", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -401,6 +446,8 @@ def main():
         line["adjoint"] = adjoint_rate(api, torch, out, N)
         line["merge_net"] = merge_net_rate(api, torch, out)
         line["narrow_u8"] = narrow_rate(api, torch, vol_np, out)
+    if not args.no_planes:
+        line["plane_detection"] = planes_rate(api, torch, out)
     del ws
     torch.cuda.empty_cache()
     if not args.no_batched:

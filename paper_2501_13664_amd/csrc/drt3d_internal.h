@@ -173,7 +173,11 @@ hipError_t launch_argmax(int is_float, const void* p, long long n, void* pv, lon
 hipError_t launch_plane_peaks(int is_float, int write, const void* p, int N, int nk, const PlaneFrames& F,
                               const long long* top, const double* thr, double tol2, int* counts,
                               const long long* offsets, long long* bins, long long cap, hipStream_t s);
-hipError_t launch_peak_scan(const int* counts, long long m, long long* offsets, long long* count, hipStream_t s);
+long long scan_chunks(long long m);
+// offsets[i] = counts[0] + ... + counts[i-1]; count[0] = 1 + the total;
+// csum: scan_chunks(m) int64 of scratch
+hipError_t launch_peak_scan(const int* counts, long long m, long long* offsets, long long* csum, long long* count,
+                            hipStream_t s);
 hipError_t launch_scatter_ones(const long long* bins, const long long* count, long long cap, uint32_t* marker,
                                long long n, uint32_t one, hipStream_t s);
 

@@ -60,25 +60,40 @@ __device__ __forceinline__ void block_best(T& v, long long& i)
             if (better(sv[q], si[q], v, i)) { v = sv[q]; i = si[q]; }
 }
 
-// per block: the best (value, index) of its grid-stride share of p[0, n)
+template <typename T>
+__device__ __forceinline__ T from_bits32(uint32_t u);
+template <>
+__device__ __forceinline__ int from_bits32<int>(uint32_t u) { return (int)u; }
+template <>
+__device__ __forceinline__ float from_bits32<float>(uint32_t u) { return __uint_as_float(u); }
+
+// per block: the best (value, index) of its grid-stride share of the n = 4 nq
+// elements, read as 16-byte quads, four quads in flight per lane
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-argmax_partial_kernel(const T* __restrict__ p, long long n, T* __restrict__ pv, long long* __restrict__ pi)
+argmax_partial_kernel(const uint4* __restrict__ p4, long long nq, T* __restrict__ pv, long long* __restrict__ pi)
 {
+    const long long n = 4 * nq;
     T bv = lowest_of<T>();
     long long bi = n;  // "none": any element ranks above it
     const long long stride = (long long)gridDim.x * kBlock;
-    for (long long i0 = (long long)blockIdx.x * kBlock + threadIdx.x; i0 < n; i0 += 4 * stride) {
-        T v[4];
+    for (long long q0 = (long long)blockIdx.x * kBlock + threadIdx.x; q0 < nq; q0 += 4 * stride) {
+        uint4 v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const long long i = i0 + u * stride;
-            v[u] = i < n ? p[i] : lowest_of<T>();
+            const long long q = q0 + u * stride;
+            v[u] = q < nq ? p4[q] : make_uint4(0u, 0u, 0u, 0u);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const long long i = i0 + u * stride;
-            if (i < n && better(v[u], i, bv, bi)) { bv = v[u]; bi = i; }
+            const long long q = q0 + u * stride;
+            if (q >= nq) continue;
+            const uint32_t e[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const T x = from_bits32<T>(e[c]);
+                if (better(x, 4 * q + c, bv, bi)) { bv = x; bi = 4 * q + c; }
+            }
         }
     }
     block_best(bv, bi);
@@ -150,9 +165,9 @@ __device__ __forceinline__ bool local_max(const T* __restrict__ Rj, int N, int E
     return true;
 }
 
-// One wavefront per output column (j, s1, s2), lanes along dd. WRITE = 0:
-// counts[column] = number of qualifying bins. WRITE = 1: their flat indices
-// go to bins[1 + offsets[column] + rank] while that is below cap.
+// Wavefronts stride over the output columns (j, s1, s2), lanes along dd.
+// WRITE = 0: counts[column] = number of qualifying bins. WRITE = 1: their
+// flat indices go to bins[1 + offsets[column] + rank] while that is below cap.
 template <typename T, int WRITE>
 __global__ void __launch_bounds__(kBlock)
 plane_peaks_kernel(const T* __restrict__ p, int N, int nk, PlaneFrames F, const long long* __restrict__ top,
@@ -161,30 +176,33 @@ plane_peaks_kernel(const T* __restrict__ p, int N, int nk, PlaneFrames F, const 
 {
     const int E = 3 * N - 2;
     const long long ncol = (long long)nk * N * N;
-    const long long col = (long long)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const long long nwaves = (long long)gridDim.x * (kBlock / 64);
     const int lane = threadIdx.x & 63;
-    if (col >= ncol) return;
-    if (WRITE && counts[col] == 0) return;
-    const int j = (int)(col / ((long long)N * N));
-    const int s1 = (int)((col / N) % N), s2 = (int)(col % N);
-    bool ortho = true;
+    long long nt[3] = {0, 0, 0};
     if (!WRITE) {
         const long long t = top[0];
         const long long per = (long long)N * N * E;
         const int tj = (int)(t / per);
         const long long tr = t - tj * per;
-        const int t1 = (int)(tr / ((long long)N * E)), t2 = (int)((tr / E) % N);
-        long long nt[3], nc[3];
-        plane_normal(F, F.ks[tj], t1, t2, N, nt);
-        plane_normal(F, F.ks[j], s1, s2, N, nc);
-        ortho = orthogonal(nt, nc, tol2);
+        plane_normal(F, F.ks[tj], (int)(tr / ((long long)N * E)), (int)((tr / E) % N), N, nt);
     }
-    int cnt = 0;
-    if (ortho) {
+    const double th = thr[0];
+    for (long long col = (long long)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); col < ncol; col += nwaves) {
+        if (WRITE && counts[col] == 0) continue;
+        const int j = (int)(col / ((long long)N * N));
+        const int s1 = (int)((col / N) % N), s2 = (int)(col % N);
+        if (!WRITE) {
+            long long nc[3];
+            plane_normal(F, F.ks[j], s1, s2, N, nc);
+            if (!orthogonal(nt, nc, tol2)) {
+                if (lane == 0) counts[col] = 0;
+                continue;
+            }
+        }
         const T* Rj = p + (long long)j * N * N * E;
         const long long cbase = col * E;
-        const double th = thr[0];
         const long long off = WRITE ? offsets[col] : 0;
+        int cnt = 0;
         for (int d0 = 0; d0 < E; d0 += 64) {
             const int dd = d0 + lane;
             bool q = false;
@@ -199,37 +217,80 @@ plane_peaks_kernel(const T* __restrict__ p, int N, int nk, PlaneFrames F, const 
             }
             cnt += __popcll(m);
         }
+        if (!WRITE && lane == 0) counts[col] = cnt;
     }
-    if (!WRITE && lane == 0) counts[col] = cnt;
 }
 
-// Exclusive prefix sums of counts[0, m) into offsets, and count[0] = 1 + the
-// total (the dominant bin plus the qualifying ones). One work group.
-constexpr int kScanBlock = 1024;
-__global__ void __launch_bounds__(kScanBlock)
-peak_scan_kernel(const int* __restrict__ counts, long long m, long long* __restrict__ offsets,
-                 long long* __restrict__ count)
+// Exclusive prefix sums of counts[0, m) into offsets, in three phases over
+// chunks of kScanChunk counts: the chunk sums, their scan (one work group,
+// which also writes count[0] = 1 + the total: the dominant bin plus the
+// qualifying ones), then each chunk's scan plus its offset.
+constexpr int kScanPer = 16;
+constexpr int kScanChunk = kBlock * kScanPer;
+
+__device__ __forceinline__ long long block_inclusive_scan(long long x)
 {
-    __shared__ long long part[kScanBlock];
-    const long long chunk = (m + kScanBlock - 1) / kScanBlock;
-    const long long b0 = chunk * threadIdx.x;
-    const long long b = b0 < m ? b0 : m, e = b + chunk < m ? b + chunk : m;
-    long long s = 0;
-    for (long long i = b; i < e; ++i) s += counts[i];
-    part[threadIdx.x] = s;
+    __shared__ long long sh[kBlock];
+    sh[threadIdx.x] = x;
     __syncthreads();
-    for (int h = 1; h < kScanBlock; h <<= 1) {
-        const long long add = threadIdx.x >= (unsigned)h ? part[threadIdx.x - h] : 0;
+    for (int h = 1; h < kBlock; h <<= 1) {
+        const long long add = (int)threadIdx.x >= h ? sh[threadIdx.x - h] : 0;
         __syncthreads();
-        part[threadIdx.x] += add;
+        sh[threadIdx.x] += add;
         __syncthreads();
     }
-    long long run = part[threadIdx.x] - s;  // exclusive prefix of this thread's chunk
+    return sh[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kBlock)
+scan_chunk_sums_kernel(const int* __restrict__ counts, long long m, long long* __restrict__ csum)
+{
+    const long long b = (long long)blockIdx.x * kScanChunk + (long long)threadIdx.x * kScanPer;
+    long long s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i)
+        if (b + i < m) s += counts[b + i];
+    s = block_inclusive_scan(s);
+    if (threadIdx.x == kBlock - 1) csum[blockIdx.x] = s;
+}
+
+// in place: csum[c] becomes the exclusive prefix of the chunk sums
+__global__ void __launch_bounds__(kBlock)
+scan_chunk_offsets_kernel(long long* __restrict__ csum, long long nc, long long* __restrict__ count)
+{
+    const long long per = (nc + kBlock - 1) / kBlock;
+    const long long b0 = per * threadIdx.x;
+    const long long b = b0 < nc ? b0 : nc, e = b + per < nc ? b + per : nc;
+    long long s = 0;
+    for (long long i = b; i < e; ++i) s += csum[i];
+    const long long incl = block_inclusive_scan(s);
+    long long run = incl - s;
     for (long long i = b; i < e; ++i) {
-        offsets[i] = run;
-        run += counts[i];
+        const long long c = csum[i];
+        csum[i] = run;
+        run += c;
     }
-    if (threadIdx.x == kScanBlock - 1) count[0] = 1 + part[kScanBlock - 1];
+    if (threadIdx.x == kBlock - 1) count[0] = 1 + incl;
+}
+
+__global__ void __launch_bounds__(kBlock)
+scan_chunk_write_kernel(const int* __restrict__ counts, long long m, const long long* __restrict__ coff,
+                        long long* __restrict__ offsets)
+{
+    const long long b = (long long)blockIdx.x * kScanChunk + (long long)threadIdx.x * kScanPer;
+    int c[kScanPer];
+    long long s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        c[i] = b + i < m ? counts[b + i] : 0;
+        s += c[i];
+    }
+    long long run = coff[blockIdx.x] + block_inclusive_scan(s) - s;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        if (b + i < m) offsets[b + i] = run;
+        run += c[i];
+    }
 }
 
 // marker[bins[i]] = one for i < min(count[0], cap); indices outside [0, n)
@@ -249,20 +310,23 @@ scatter_ones_kernel(const long long* __restrict__ bins, const long long* __restr
 
 int argmax_parts(long long n)
 {
-    return (int)std::max(1LL, std::min(1024LL, (n + 4LL * kBlock - 1) / (4LL * kBlock)));
+    const long long nq = n / 4;
+    return (int)std::max(1LL, std::min(2048LL, (nq + 4LL * kBlock - 1) / (4LL * kBlock)));
 }
+
+long long scan_chunks(long long m) { return std::max(1LL, (m + kScanChunk - 1) / kScanChunk); }
 
 hipError_t launch_argmax(int is_float, const void* p, long long n, void* pv, long long* pi, int nparts, double rel,
                          long long* top, double* thr, long long* bins, hipStream_t s)
 {
+    if (n % 4) return hipErrorInvalidValue;  // DRT outputs hold a multiple of 4 elements
+    const uint4* p4 = (const uint4*)p;
     if (is_float) {
-        hipLaunchKernelGGL(argmax_partial_kernel<float>, dim3(nparts), dim3(kBlock), 0, s, (const float*)p, n,
-                           (float*)pv, pi);
+        hipLaunchKernelGGL(argmax_partial_kernel<float>, dim3(nparts), dim3(kBlock), 0, s, p4, n / 4, (float*)pv, pi);
         hipLaunchKernelGGL(argmax_final_kernel<float>, dim3(1), dim3(kBlock), 0, s, (const float*)p, n,
                            (const float*)pv, (const long long*)pi, nparts, rel, top, thr, bins);
     } else {
-        hipLaunchKernelGGL(argmax_partial_kernel<int>, dim3(nparts), dim3(kBlock), 0, s, (const int*)p, n, (int*)pv,
-                           pi);
+        hipLaunchKernelGGL(argmax_partial_kernel<int>, dim3(nparts), dim3(kBlock), 0, s, p4, n / 4, (int*)pv, pi);
         hipLaunchKernelGGL(argmax_final_kernel<int>, dim3(1), dim3(kBlock), 0, s, (const int*)p, n, (const int*)pv,
                            (const long long*)pi, nparts, rel, top, thr, bins);
     }
@@ -274,7 +338,7 @@ hipError_t launch_plane_peaks(int is_float, int write, const void* p, int N, int
                               const long long* offsets, long long* bins, long long cap, hipStream_t s)
 {
     const long long ncol = (long long)nk * N * N;
-    const dim3 grid((unsigned)((ncol + kBlock / 64 - 1) / (kBlock / 64)));
+    const dim3 grid((unsigned)std::min(4096LL, (ncol + kBlock / 64 - 1) / (kBlock / 64)));
 #define DRT3D_PEAKS(T, W)                                                                                      \
     hipLaunchKernelGGL((plane_peaks_kernel<T, W>), grid, dim3(kBlock), 0, s, (const T*)p, N, nk, F, top, thr, \
                        tol2, counts, offsets, bins, cap)
@@ -289,9 +353,14 @@ hipError_t launch_plane_peaks(int is_float, int write, const void* p, int N, int
     return hipGetLastError();
 }
 
-hipError_t launch_peak_scan(const int* counts, long long m, long long* offsets, long long* count, hipStream_t s)
+hipError_t launch_peak_scan(const int* counts, long long m, long long* offsets, long long* csum, long long* count,
+                            hipStream_t s)
 {
-    hipLaunchKernelGGL(peak_scan_kernel, dim3(1), dim3(kScanBlock), 0, s, counts, m, offsets, count);
+    const long long nc = scan_chunks(m);
+    hipLaunchKernelGGL(scan_chunk_sums_kernel, dim3((unsigned)nc), dim3(kBlock), 0, s, counts, m, csum);
+    hipLaunchKernelGGL(scan_chunk_offsets_kernel, dim3(1), dim3(kBlock), 0, s, csum, nc, count);
+    hipLaunchKernelGGL(scan_chunk_write_kernel, dim3((unsigned)nc), dim3(kBlock), 0, s, counts, m,
+                       (const long long*)csum, offsets);
     return hipGetLastError();
 }
 

@@ -1558,7 +1558,7 @@ int drt3d_merge_net(const void* proj, void* net, int N, int dtype, void* stream)
 // threshold; backprojection of listed bins through the adjoint.
 namespace {
 struct DetectLayout {
-    size_t pv = 0, pi = 0, top = 0, thr = 0, counts = 0, offsets = 0, total = 0;
+    size_t pv = 0, pi = 0, top = 0, thr = 0, counts = 0, offsets = 0, csum = 0, total = 0;
 };
 void detect_layout(int N, uint32_t mask, DetectLayout& L)
 {
@@ -1572,6 +1572,7 @@ void detect_layout(int N, uint32_t mask, DetectLayout& L)
     L.thr = o; o = align256(o + 8);
     L.counts = o; o = align256(o + 4 * (size_t)ncol);
     L.offsets = o; o = align256(o + 8 * (size_t)ncol);
+    L.csum = o; o = align256(o + 8 * (size_t)scan_chunks(ncol));
     L.total = o;
 }
 void plane_frames(uint32_t mask, PlaneFrames& F)
@@ -1627,7 +1628,7 @@ int drt3d_detect_planes(const void* proj, int N, uint32_t mask, int dtype, doubl
     const double tol2 = cos_tol * cos_tol;
     HIP_TRY(launch_argmax(is_float, proj, n, w + L.pv, (long long*)(w + L.pi), parts, rel_threshold, top, thr, bins, s));
     HIP_TRY(launch_plane_peaks(is_float, 0, proj, N, nk, F, top, thr, tol2, counts, offsets, bins, cap, s));
-    HIP_TRY(launch_peak_scan(counts, ncol, offsets, count, s));
+    HIP_TRY(launch_peak_scan(counts, ncol, offsets, (long long*)(w + L.csum), count, s));
     HIP_TRY(launch_plane_peaks(is_float, 1, proj, N, nk, F, top, thr, tol2, counts, offsets, bins, cap, s));
     return DRT3D_OK;
 }
