@@ -179,7 +179,11 @@ struct Tuning {
     int kx[8] = {0}, ky[8] = {0};
     int lds_elems = 18432;  // LDS budget of one work group, in 4-byte elements (72 KB: two per CU)
     int waves = 8;          // wavefronts per work group (upper bound)
+    int adj_lds_elems = 0;  // the adjoint's passes other than a fused last pass; 0: lds_elems
 };
+
+// LDS budget of an adjoint pass (the fused last pass keeps lds_elems)
+static int adj_lds_of(const Tuning& t) { return t.adj_lds_elems > 0 ? t.adj_lds_elems : t.lds_elems; }
 
 static const int kMaxPassSlots = 256;  // 2^(kx+ky) columns per group at most
 
@@ -212,7 +216,7 @@ static const MeasuredTuning kMeasured[] = {
     {6, 0, "p=3.3,3.3;lds=20480;waves=8"},     {6, 1, "p=3.3,3.3;lds=24576;waves=8"},
     {7, 0, "p=2.2,2.3,3.2;lds=12288;waves=8"}, {7, 1, "p=2.2,2.3,3.2;lds=14336;waves=8"},
     {8, 0, "p=3.3,2.3,3.2;lds=14336;waves=8"}, {8, 1, "p=2.3,3.3,3.2;lds=24576;waves=8"},
-    {9, 0, "p=3.3,3.3,3.3;lds=14336;waves=8"}, {9, 1, "p=3.3,3.3,3.3;lds=14336;waves=16"},
+    {9, 0, "p=3.3,3.3,3.3;lds=14336;waves=8;alds=13312"}, {9, 1, "p=3.3,3.3,3.3;lds=14336;waves=16"},
 };
 
 static Tuning default_tuning(int n, int is_float)
@@ -229,6 +233,7 @@ static std::string tuning_to_string(const Tuning& t)
     std::string s = "p=";
     for (int i = 0; i < t.np; ++i) s += (i ? "," : "") + std::to_string(t.kx[i]) + "." + std::to_string(t.ky[i]);
     s += ";lds=" + std::to_string(t.lds_elems) + ";waves=" + std::to_string(t.waves);
+    if (t.adj_lds_elems > 0) s += ";alds=" + std::to_string(t.adj_lds_elems);
     return s;
 }
 
@@ -255,7 +260,13 @@ static bool tuning_from_string(const char* s, int n, Tuning& t)
     p = e;
     if (strncmp(p, ";waves=", 7)) return false;
     r.waves = (int)strtol(p + 7, &e, 10);
-    if (*e) return false;
+    p = e;
+    if (!strncmp(p, ";alds=", 6)) {
+        r.adj_lds_elems = (int)strtol(p + 6, &e, 10);
+        p = e;
+        if (r.adj_lds_elems < 1024 || r.adj_lds_elems > 40960) return false;
+    }
+    if (*p) return false;
     int sx = 0, sy = 0;
     for (int i = 0; i < r.np; ++i) {
         if (r.kx[i] < 0 || r.ky[i] < 0 || r.kx[i] + r.ky[i] < 1) return false;
@@ -906,7 +917,8 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             d.N = N; d.n = n; d.adjoint = adjoint;
             d.mx0 = g.mx0; d.Kx = g.Kx; d.my0 = g.my0; d.Ky = g.Ky;
             int T, H, L, ntl;
-            if (!choose_tiles(g, adjoint, t.lds_elems, T, H, L, ntl))
+            const int pass_lds = adjoint && !(step == np - 1 && fuse_last) ? adj_lds_of(t) : t.lds_elems;
+            if (!choose_tiles(g, adjoint, pass_lds, T, H, L, ntl))
                 return fail(DRT3D_EINVAL, "tuning %s cannot fit pass %d in LDS", tuning_to_string(t).c_str(), pi);
             d.T = T; d.H = H; d.L = L; d.Lp = L + pass_pad(g); d.ntiles = ntl;
             d.groups_x = N >> g.Kx;
@@ -1948,11 +1960,11 @@ int drt3d_set_tuning(int N, int dtype, const char* text)
     if (!text) return fail(DRT3D_EINVAL, "tuning text is NULL");
     Tuning t;
     if (!tuning_from_string(text, ilog2_exact(N), t)) return fail(DRT3D_EINVAL, "cannot parse tuning '%s'", text);
-    // every pass must fit
-    for (int adj = 0; adj < 2; ++adj)
+    // every pass must fit, the adjoint's under both of its budgets
+    for (int adj = 0; adj < 3; ++adj)
         for (const PassGeom& g : drt_passes(N, t)) {
             int T, H, L, nt;
-            if (!choose_tiles(g, adj, t.lds_elems, T, H, L, nt))
+            if (!choose_tiles(g, adj > 0, adj == 2 ? adj_lds_of(t) : t.lds_elems, T, H, L, nt))
                 return fail(DRT3D_EINVAL, "tuning '%s' does not fit LDS", text);
         }
     put_tuning(N, dtype == DRT3D_F32, t);
@@ -2044,11 +2056,11 @@ int drt3d_autotune(int N, int dtype, const void* vol, void* out, void* workspace
         return DRT3D_OK;
     };
     auto fits = [&](const Tuning& t) {
-        if ((size_t)t.lds_elems * 4 > (size_t)di.max_lds) return false;
-        for (int adj = 0; adj < 2; ++adj)
+        if ((size_t)std::max(t.lds_elems, adj_lds_of(t)) * 4 > (size_t)di.max_lds) return false;
+        for (int adj = 0; adj < 3; ++adj)
             for (const PassGeom& g : drt_passes(N, t)) {
                 int T, H, L, nt;
-                if (!choose_tiles(g, adj, t.lds_elems, T, H, L, nt)) return false;
+                if (!choose_tiles(g, adj > 0, adj == 2 ? adj_lds_of(t) : t.lds_elems, T, H, L, nt)) return false;
             }
         return true;
     };

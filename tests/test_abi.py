@@ -165,6 +165,13 @@ def test_tuning_text_round_trip_and_rejection():
                     b"garbage", b""):
             assert L.drt3d_set_tuning(N, dt, bad) == EINVAL, bad
         assert L.drt3d_tuning_string(N, dt) == b"p=2.2,2.2,2.2;lds=12288;waves=4"
+        # an own LDS budget for the adjoint's passes
+        assert L.drt3d_set_tuning(N, dt, b"p=3.3,3.3;lds=20480;waves=8;alds=6144") == OK
+        assert L.drt3d_tuning_string(N, dt) == b"p=3.3,3.3;lds=20480;waves=8;alds=6144"
+        for bad in (b"p=3.3,3.3;lds=20480;waves=8;alds=512",     # below the smallest budget
+                    b"p=3.3,3.3;lds=20480;waves=8;alds=2048",    # 64 columns cannot fit 2048 elements
+                    b"p=3.3,3.3;lds=20480;waves=8;alds=6144;"):
+            assert L.drt3d_set_tuning(N, dt, bad) == EINVAL, bad
     finally:
         assert L.drt3d_set_tuning(N, dt, default) == OK
 

@@ -164,7 +164,8 @@ TUNINGS = {
     32: ["p=3.3,2.2;lds=20480;waves=8", "p=2.2,3.3;lds=6144;waves=8", "p=1.2,2.1,2.2;lds=2048;waves=4",
          "p=5.0,0.5;lds=40960;waves=8", "p=4.4,1.1;lds=40960;waves=8", "p=2.3,3.2;lds=8192;waves=4"],
     64: ["p=3.3,3.3;lds=20480;waves=8", "p=3.3,3.3;lds=6144;waves=8", "p=2.2,2.2,2.2;lds=12288;waves=4",
-         "p=4.3,2.3;lds=16384;waves=8"],
+         "p=4.3,2.3;lds=16384;waves=8", "p=3.3,3.3;lds=14336;waves=8;alds=6144",
+         "p=2.2,2.2,2.2;lds=6144;waves=8;alds=20480"],
 }
 
 
