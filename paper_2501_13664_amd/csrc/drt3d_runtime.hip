@@ -206,7 +206,8 @@ static Tuning rule_tuning(int n)
     return t;
 }
 
-// Choices of drt3d_autotune on an MI355X (gfx950), per size class and dtype.
+// Choices of drt3d_autotune on an MI355X (gfx950), per size class and dtype;
+// the adjoint budgets (alds) from timing the adjoint's passes alone.
 struct MeasuredTuning {
     int n, is_float;
     const char* text;
