@@ -821,13 +821,15 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 // adds each result into registers in physical column order, and writes the
 // block once. The volume is written once instead of once per dodecant with
 // three read-backs. Slots 4g..4g+3 of the descriptor are group g's dodecants.
-// Its sums and tails take ~40 more registers than a plain pass: 128 per lane
-// (4 waves per SIMD, two work groups per CU) keeps them out of scratch.
+// Each step's columns load straight into LDS (buffer loads to LDS, no
+// register staging), so the sums and tails fit in 80 registers: three work
+// groups of eight wavefronts per CU, whose load phases overlap each other's
+// stages (two groups of sixteen).
 // K: stages per axis of the pass (blocks of B x B columns, B = 2^K); NW:
 // wavefronts, a multiple of B (wave w owns slots p = w + NW i, whose x index
 // w mod B is fixed per wave, as in drt_pass_fast).
 template <typename T, int K, int NCH, int NW>
-__global__ void __launch_bounds__(64 * NW, 4)
+__global__ void __launch_bounds__(64 * NW, NW == 16 ? 8 : 6)
 drt_adj_last_group(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 {
     constexpr int B = 1 << K, NS = B * B, SPW = NS / NW, L = 64 * NCH, NDOD = 4;
@@ -873,7 +875,6 @@ drt_adj_last_group(const DrtDesc* __restrict__ descs, int ndesc, long long total
         for (int p = wave; p <= NS; p += NW)
             if (lane < pad) lds[p * Lp + lane] = zero_of<T>();
 
-        uint32_t v[SPW][NCH];
         T acc[SPW][NCH + 1];  // this tile's sums over the dodecants, per physical column and store chunk
         uint32_t carry[SPW];  // the previous tile's tail sums (lane k: displacement fbeg + k)
         T ncarry[SPW];        // this tile's tail sums
@@ -881,6 +882,8 @@ drt_adj_last_group(const DrtDesc* __restrict__ descs, int ndesc, long long total
         for (int i = 0; i < SPW; ++i) carry[i] = 0u;
 
         // step j = tile * 4 + r loads dodecant r's slope columns for the tile
+        // into their LDS slots; lanes past the input extent load zeros
+        typedef __attribute__((address_space(3))) void lds_void;
         auto issue_loads = [&](int j) {
             const int tile = j >> 2, r = j & 3;
             const int s = NDOD * grp + r;
@@ -896,28 +899,28 @@ drt_adj_last_group(const DrtDesc* __restrict__ descs, int ndesc, long long total
                 const int colo = so + bitrev(y_of(i), K) * d->P_in;
                 const int dl = d0 + lane;
                 const int ob = 4 * (colo + dl);
+                T* dst = lds + slot_offset(wave + i * NW, Lp, pad);
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
                     const bool in = (unsigned)(dl + 64 * c) < (unsigned)d->E_in;
-                    v[i][c] = bload(rs, in ? ob + 256 * c : -1);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(dst + 64 * c), 4, in ? ob + 256 * c : -1,
+                                                            0, 0, 0);
                 }
             }
         };
 
         const int nsteps = ntiles * NDOD;
-        issue_loads(0);
+        __syncthreads();  // the slot pads are written
         for (int j = 0; j < nsteps; ++j) {
             const int tile = j >> 2, r = j & 3;
             const int d0 = tile * T_;
             const bool last_tile = tile + 1 == ntiles;
-#pragma unroll
-            for (int i = 0; i < SPW; ++i) {
-                T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + lane;
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) sl[64 * c] = from_bits<T>(v[i][c]);
-            }
-            __syncthreads();
-            if (j + 1 < nsteps) issue_loads(j + 1);
+            issue_loads(j);
+            // this wave's loads have landed in LDS; then every wave's have
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (0 << 8) | (0 << 14));
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
             run_stages<T, NCH>(lds, Lp, pad, NCH, K, K, 1, wave, NW, lane);
             __syncthreads();
             // the wave's physical columns (pa, pb) = (px, y_of(i)); a column's

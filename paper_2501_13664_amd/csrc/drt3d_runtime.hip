@@ -861,12 +861,16 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
         int T0, H0, L0, nt0;
         int w0 = std::min(t.waves, std::max(1, 1 << (g0.Kx + g0.Ky - 1)));
         if (w0 > 8 && !(g0.Kx == 3 && g0.Ky == 3)) w0 = 8;
-        // 3.3 with eight wavefronts keeps 8 columns per wave in registers: up
-        // to 4 chunks fit without spilling its sums
-        const int max_nch = g0.Kx == 3 && w0 == 8 ? 4 : 6;
+        // the tile widths whose sums fit the fused kernel's register budget
+        // without spilling (3.3: 80 registers at eight wavefronts, 64 at
+        // sixteen; 2.2 keeps 2 columns per wave)
+        auto fused_fits = [&](int K, int waves, int nch) {
+            if (K == 2) return nch <= 6;
+            return waves == 8 ? nch <= 3 : (nch != 2 && nch <= 5);
+        };
         fuse_last = runs4 && chunk == nd && g0.Kx == g0.Ky && (g0.Kx == 2 || g0.Kx == 3) && (w0 == 8 || w0 == 16) &&
-                    choose_tiles(g0, 1, t.lds_elems, T0, H0, L0, nt0) && (L0 & 63) == 0 && (L0 >> 6) <= max_nch &&
-                    drt_adj_group_kernel(is_float, g0.Kx, L0 >> 6, w0) != nullptr;
+                    choose_tiles(g0, 1, t.lds_elems, T0, H0, L0, nt0) && (L0 & 63) == 0 &&
+                    fused_fits(g0.Kx, w0, L0 >> 6) && drt_adj_group_kernel(is_float, g0.Kx, L0 >> 6, w0) != nullptr;
         fuse_waves = w0;
         if (!fuse_last) {
             int by[3][4], c[3] = {0, 0, 0}, q = 0;
