@@ -234,10 +234,15 @@ int drt3d_inverse_lambdas(int N, double* lams, void* workspace, size_t workspace
  * by the order in which the stage sums are rounded. */
 int drt3d_autotune(int N, int dtype, const void* vol, void* out,
                    void* workspace, size_t workspace_bytes, void* stream);
-/* Current tuning choice of size class N as text (for logs and tests). */
+/* Current tuning choice of size class N as text (for logs and tests):
+ * "p=<kx>.<ky>,...;lds=<elements>;waves=<w>[;alds=<elements>]", the stages
+ * per axis of each pass, the LDS budget of a work group in 4-byte elements,
+ * the wavefronts per work group, and optionally a separate LDS budget for the
+ * adjoint's passes other than a fused last pass. */
 const char* drt3d_tuning_string(int N, int dtype);
-/* Force a tuning choice from its text form (as printed by drt3d_tuning_string);
- * used by determinism tests. */
+/* Force a tuning choice from its text form (as printed by drt3d_tuning_string;
+ * every pass of forward and adjoint must fit its LDS budget, else
+ * DRT3D_EINVAL); used by determinism tests. */
 int drt3d_set_tuning(int N, int dtype, const char* text);
 
 /* ---- profiling -------------------------------------------------------------- */
