@@ -189,8 +189,10 @@ plane_peaks_kernel(const T* __restrict__ p, int N, int nk, PlaneFrames F, const 
     const double th = thr[0];
     for (long long col = (long long)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); col < ncol; col += nwaves) {
         if (WRITE && counts[col] == 0) continue;
-        const int j = (int)(col / ((long long)N * N));
-        const int s1 = (int)((col / N) % N), s2 = (int)(col % N);
+        // N is a power of two: the column's (j, s1, s2) by shifts
+        const int lg = 31 - __clz(N);
+        const int j = (int)(col >> (2 * lg));
+        const int s1 = (int)(col >> lg) & (N - 1), s2 = (int)col & (N - 1);
         if (!WRITE) {
             long long nc[3];
             plane_normal(F, F.ks[j], s1, s2, N, nc);
@@ -203,19 +205,25 @@ plane_peaks_kernel(const T* __restrict__ p, int N, int nk, PlaneFrames F, const 
         const long long cbase = col * E;
         const long long off = WRITE ? offsets[col] : 0;
         int cnt = 0;
-        for (int d0 = 0; d0 < E; d0 += 64) {
-            const int dd = d0 + lane;
-            bool q = false;
-            if (dd < E) {
-                const T v = p[cbase + dd];
-                q = (double)v >= th && local_max(Rj, N, E, s1, s2, dd, v);
+        // four 64-displacement chunks per round, their loads in flight together
+        for (int d0 = 0; d0 < E; d0 += 256) {
+            T v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int dd = d0 + 64 * u + lane;
+                v[u] = dd < E ? p[cbase + dd] : lowest_of<T>();
             }
-            const unsigned long long m = __ballot(q);
-            if (WRITE && q) {
-                const long long pos = 1 + off + cnt + __popcll(m & ((1ULL << lane) - 1));
-                if (pos < cap) bins[pos] = cbase + dd;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int dd = d0 + 64 * u + lane;
+                const bool q = dd < E && (double)v[u] >= th && local_max(Rj, N, E, s1, s2, dd, v[u]);
+                const unsigned long long m = __ballot(q);
+                if (WRITE && q) {
+                    const long long pos = 1 + off + cnt + __popcll(m & ((1ULL << lane) - 1));
+                    if (pos < cap) bins[pos] = cbase + dd;
+                }
+                cnt += __popcll(m);
             }
-            cnt += __popcll(m);
         }
         if (!WRITE && lane == 0) counts[col] = cnt;
     }
