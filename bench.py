@@ -12,8 +12,14 @@ events recorded on the launch stream around every launch of the timed
 region; its algorithmic bytes are the reads of each pass's input extent plus
 the writes of its output extent; `traffic` is the HBM bytes per launch from
 the committed rocprofv3 counter summary when it was taken on the current
-sources. `cpu_baseline` times the oracle's naive Algorithm 1 on one dodecant of
-the same cube (scaled to the job).
+sources. `compulsory_floor` relates the time per transform to the least HBM
+traffic any implementation needs (read the volume once per dodecant, write the
+output once) at the 8 TB/s peak. `cpu_baseline` times the oracle's naive
+Algorithm 1 on the same cube on the host: one thread on one dodecant, and all
+12 dodecants on parallel threads (the whole job); that leg, the only one that
+runs the oracle, also measures each float32 result of the batched and
+differentiable legs against the FP64 oracle (normwise error and
+max |err| / R(|f|), written into those legs as `fp64_error`).
 
 Further measurements ride along (skipped with --no-adjoint / --no-batched /
 --no-diff / --no-djt / --no-inverse): the adjoint of the benchmark's
@@ -44,6 +50,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def floor_record(N, ms):
+    """The transform's compulsory HBM traffic (read the input once per
+    dodecant, write the 12 N^2 (3N-2) int32 output once), its time at the 8 TB/s
+    peak, and the measured time per transform as a multiple of it."""
+    nbytes = 12 * 4.0 * N ** 3 + 12 * 4.0 * N * N * (3 * N - 2)
+    floor_ms = nbytes / (HBM_PEAK_GBS * 1e9) * 1e3
+    return {"bytes": nbytes, "floor_ms": floor_ms, "ms_per_transform": ms, "ratio_to_floor": ms / floor_ms}
 
 
 def updates(N, ndod=12):
@@ -82,20 +97,110 @@ def _traffic_record(kernel):
     return ent.get("bytes_per_launch")
 
 
-def cpu_baseline(vol):
+def _host_info():
+    """Host CPU model and thread counts as the GPU machine's own host reports them."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    if model is None:
+        try:
+            import subprocess
+            out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+            model = next((l.split(":", 1)[1].strip() for l in out.splitlines() if l.startswith("Model name")), None)
+        except OSError:
+            pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    avail = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemAvailable:"):
+                avail = int(line.split()[1]) * 1024
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "affinity": affinity, "mem_available_bytes": avail}
+
+
+def _fp64_errors(y32, y64, r_abs):
+    """Normwise relative L2 error of a float32 result against FP64, and the
+    largest |y32 - y64| / R(|f|) (R(|f|): the same transform of |f| in FP64)."""
+    y32 = np.asarray(y32, dtype=np.float64)
+    d = y32 - y64
+    nw = float(np.linalg.norm(d) / max(np.linalg.norm(y64), 1e-300))
+    m = r_abs > 0
+    mx = float(np.max(np.abs(d[m]) / r_abs[m])) if m.any() else 0.0
+    if (~m).any():
+        mx = max(mx, float("inf") if np.any(d[~m] != 0) else 0.0)
+    return nw, mx
+
+
+def cpu_baseline(vol, float_checks=()):
+    """The oracle on the GPU machine's host cores: its naive Algorithm 1 on the
+    N=512 benchmark cube, once on one thread for dodecant 0 and once for all 12
+    dodecants on parallel threads (one dodecant per thread; the oracle's C
+    calls release the GIL), so `value` is the whole job's rate on `cores`
+    threads.
+
+    This leg is also where the float legs' results meet the FP64 oracle (the
+    only part of the benchmark that runs it): each entry of float_checks is
+    (leg dict, name, float32 result, kind, input, N) and gets its normwise
+    error and max |err| / R(|f|) written into leg["fp64_error"][name]."""
     import oracle
+    from concurrent.futures import ThreadPoolExecutor
     N = vol.shape[0]
+    host = _host_info()
     t0 = time.perf_counter()
     oracle.rec_drt(vol, 0x001)
-    dt = time.perf_counter() - t0
-    return {
-        "value": updates(N, 1) / dt,
+    t1 = time.perf_counter() - t0
+    # one dodecant holds about 4 N^2 (3N) int64 cells of buffers and output
+    per_thread = 4 * N * N * 3 * N * 8
+    threads = min(12, host["affinity"] or 1, 16)
+    if host["mem_available_bytes"]:
+        threads = max(1, min(threads, int(0.6 * host["mem_available_bytes"] // per_thread)))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda k: oracle.rec_drt(vol, 1 << k).shape, range(12)))
+    tp = time.perf_counter() - t0
+    res = {
+        "value": updates(N, 12) / tp,
         "unit": "voxel-stage updates/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": "dodecant 0 of the same N=%d cube (1/12 of the job), naive Algorithm 1 on "
-                  "full-extent int64 buffers, one thread: %.2f s" % (N, dt),
+        "sample": "the whole job: all 12 dodecants of the same N=%d cube, naive Algorithm 1 on full-extent "
+                  "int64 buffers, one dodecant per thread on %d threads: %.2f s; one thread on dodecant 0: "
+                  "%.2f s" % (N, threads, tp, t1),
+        "one_thread": {"value": updates(N, 1) / t1, "seconds_one_dodecant": t1},
+        "parallel": {"threads": threads, "seconds_12_dodecants": tp, "value": updates(N, 12) / tp},
+        "host": host,
     }
+    t0 = time.perf_counter()
+
+    def check(item):
+        leg, name, y32, kind, inp, Nc = item
+        x64 = np.asarray(inp, dtype=np.float64)
+        if kind == "drt":
+            y64, r = oracle.rec_drt(x64), oracle.rec_drt(np.abs(x64))
+        else:  # the adjoint of a projection
+            y64, r = oracle.rec_adj(x64, Nc), oracle.rec_adj(np.abs(x64), Nc)
+        return leg, name, _fp64_errors(y32, y64, r)
+
+    items = list(float_checks)
+    with ThreadPoolExecutor(max_workers=max(1, min(8, host["affinity"] or 1))) as ex:
+        for leg, name, (nw, mx) in ex.map(check, items):
+            e = leg.setdefault("fp64_error", {"tolerance": 1e-5, "results": {}})
+            e["results"][name] = {"normwise": nw, "max_over_R_abs_f": mx}
+            e["worst_normwise"] = max(e.get("worst_normwise", 0.0), nw)
+            e["worst_max_over_R_abs_f"] = max(e.get("worst_max_over_R_abs_f", 0.0), mx)
+    if items:
+        res["fp64_checks_seconds"] = time.perf_counter() - t0
+    return res
 
 
 def _best_ms(torch, fn, reps):
@@ -129,11 +234,23 @@ def batched_speedup(api, torch, reps=5):
     ref = [o.clone() for o in outs]
     bt = _best_ms(torch, batched, reps)
     same = all(torch.equal(a, b) for a, b in zip(ref, outs))
+    del ref
     U = sum(updates(c.shape[0]) for c in cubes)
-    return {"workload": "96 float32 N(0,1) cubes, seeds 1000+i: 48x32^3 + 32x64^3 + 12x128^3 + 4x256^3, "
-                        "12 dodecants",
-            "per_volume_ms": pv, "batched_ms": bt, "speedup": pv / bt, "bit_identical": same,
-            "updates": U, "batched_updates_per_s": U / (bt / 1e3)}
+    leg = {"workload": "96 float32 N(0,1) cubes, seeds 1000+i: 48x32^3 + 32x64^3 + 12x128^3 + 4x256^3, "
+                       "12 dodecants",
+           "per_volume_ms": pv, "batched_ms": bt, "speedup": pv / bt, "bit_identical": same,
+           "updates": U, "batched_updates_per_s": U / (bt / 1e3),
+           "fp64_error_sample": "every output of all 48 N=32 and 32 N=64 cubes, of the first two N=128 cubes "
+                                "and of the first N=256 cube"}
+    # the batched call's results, for the FP64 comparison in the cpu_baseline leg
+    seen = {}
+    checks = []
+    for i, (c, o) in enumerate(zip(workloads.mixed_batch(), outs)):
+        Nc = c.shape[0]
+        seen[Nc] = seen.get(Nc, 0) + 1
+        if Nc <= 64 or (Nc == 128 and seen[Nc] <= 2) or (Nc == 256 and seen[Nc] <= 1):
+            checks.append((leg, "cube%d_N%d" % (i, Nc), o.cpu().numpy(), "drt", c, Nc))
+    return leg, checks
 
 
 def differentiable_speedup(api, torch, reps=5):
@@ -165,9 +282,17 @@ def differentiable_speedup(api, torch, reps=5):
     ad = _best_ms(torch, differentiable, reps)
     same = torch.equal(state["y"].detach(), y) and torch.equal(fr.grad, x)
     U = 2 * B * updates(N)
-    return {"workload": "8 float32 N(0,1) cubes N=128 (seed 5), 12 dodecants, grad_out N(0,1) (seed 6)",
-            "per_volume_ms": pv, "autograd_ms": ad, "speedup": pv / ad, "bit_identical": same,
-            "updates": U, "autograd_updates_per_s": U / (ad / 1e3)}
+    leg = {"workload": "8 float32 N(0,1) cubes N=128 (seed 5), 12 dodecants, grad_out N(0,1) (seed 6)",
+           "per_volume_ms": pv, "autograd_ms": ad, "speedup": pv / ad, "bit_identical": same,
+           "updates": U, "autograd_updates_per_s": U / (ad / 1e3),
+           "fp64_error_sample": "every output of cubes 0 and 1: the forward R f and the gradient R^T g"}
+    f_np = workloads.normal_batch(B, N, seed=5)
+    g_np = workloads.normal_weights((B,) + api.drt3d_out_shape(N), seed=6)
+    checks = []
+    for b in (0, 1):
+        checks.append((leg, "forward_cube%d" % b, state["y"][b].detach().cpu().numpy(), "drt", f_np[b], N))
+        checks.append((leg, "backward_cube%d" % b, fr.grad[b].cpu().numpy(), "adj", g_np[b], N))
+    return leg, checks
 
 
 def adjoint_rate(api, torch, proj, N, reps=3):
@@ -440,6 +565,7 @@ def main():
             "traffic": _traffic_record(dom),
         },
         "hbm_alg_GBps_all_kernels": total_alg / (total_ms / 1e3) / 1e9,
+        "compulsory_floor": floor_record(N, ms),
         "kernels": kernels,
     }
     if not args.no_adjoint:
@@ -450,11 +576,14 @@ def main():
         line["plane_detection"] = planes_rate(api, torch, out)
     del ws
     torch.cuda.empty_cache()
+    float_checks = []
     if not args.no_batched:
-        line["batched_vs_per_volume"] = batched_speedup(api, torch)
+        line["batched_vs_per_volume"], chk = batched_speedup(api, torch)
+        float_checks += chk
         torch.cuda.empty_cache()
     if not args.no_diff:
-        line["differentiable_vs_per_volume"] = differentiable_speedup(api, torch)
+        line["differentiable_vs_per_volume"], chk = differentiable_speedup(api, torch)
+        float_checks += chk
         torch.cuda.empty_cache()
     if not args.no_djt:
         line["djt"] = djt_rate(api, torch)
@@ -463,7 +592,7 @@ def main():
         line["inverse"] = inverse_rate(api, torch)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(vol_np)
+        line["cpu_baseline"] = cpu_baseline(vol_np, float_checks)
     print(json.dumps(line), flush=True)
 
 

@@ -52,7 +52,11 @@ extern "C" {
 #endif
 
 #define DRT3D_ABI_VERSION 1
-#define DRT3D_MAX_N 1024
+/* Largest N any entry point accepts. Every kernel addresses a dodecant's output
+ * region, a stage buffer slot and the volume with 32-bit byte offsets, which
+ * hold up to N = 512 (a 512^3 int32 volume is 2^29 bytes, a dodecant of the
+ * DRT output 1.6 GB); larger N is rejected with DRT3D_EINVAL. */
+#define DRT3D_MAX_N 512
 #define DRT3D_ALL 0xFFFu
 
 typedef enum {

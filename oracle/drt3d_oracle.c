@@ -95,6 +95,13 @@ void orc_frame_to_orig(int k, int N, const int primed[3], int orig[3])
     }
 }
 
+/* Row k of the InOrder table as the oracle holds it (for the test that pins
+ * this transcription against a golden copy of the printed table).          */
+void orc_in_order_row(int k, int row[3])
+{
+    for (int i = 0; i < 3; ++i) row[i] = IN_ORDER[k][i];
+}
+
 /* Linear part of the original -> primed map as a signed permutation matrix
  * M (row-major, primed = M * orig + offset); used by the tiling tests.      */
 void orc_frame_matrix(int k, int M[9])

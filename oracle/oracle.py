@@ -24,7 +24,7 @@ _lock = threading.Lock()
 _lib = None
 
 __all__ = [
-    "build", "line", "line_recursive", "frame_to_orig", "frame_matrix",
+    "build", "line", "line_recursive", "frame_to_orig", "frame_matrix", "in_order_row",
     "drt_point", "djt_point", "adj_point", "djt_adj_point",
     "def_drt", "def_djt", "def_adj", "def_djt_adj",
     "rec_drt", "rec_djt", "rec_adj",
@@ -58,6 +58,8 @@ def _load():
         lib.orc_line_recursive.restype = c_int
         lib.orc_frame_to_orig.argtypes = [c_int, c_int, ip, ip]
         lib.orc_frame_to_orig.restype = None
+        lib.orc_in_order_row.argtypes = [c_int, ip]
+        lib.orc_in_order_row.restype = None
         lib.orc_frame_matrix.argtypes = [c_int, ip]
         lib.orc_frame_matrix.restype = None
         for suf, inp, acc, accty in (("i", i32p, i64p, ctypes.c_int64), ("f", f64p, f64p, ctypes.c_double)):
@@ -117,6 +119,13 @@ def frame_to_orig(k: int, N: int, primed) -> tuple:
     o = (ctypes.c_int * 3)()
     _load().orc_frame_to_orig(k, N, p, o)
     return tuple(o)
+
+
+def in_order_row(k: int) -> tuple:
+    """Row k of Algorithm 2's InOrder table as the oracle holds it."""
+    r = (ctypes.c_int * 3)()
+    _load().orc_in_order_row(k, r)
+    return tuple(r)
 
 
 def frame_matrix(k: int) -> np.ndarray:

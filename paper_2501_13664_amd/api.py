@@ -58,8 +58,40 @@ def _stream(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(s.cuda_stream)
 
 
+class _on_stream:
+    """Makes `stream` (if given) current for the body, so that every tensor the
+    wrapper allocates (outputs, workspace) belongs to the stream the library
+    runs on and the caching allocator does not hand the workspace out again
+    while the library's kernels still use it."""
+
+    def __init__(self, stream):
+        self.ctx = torch.cuda.stream(stream) if stream is not None else None
+
+    def __enter__(self):
+        if self.ctx is not None:
+            self.ctx.__enter__()
+        return self
+
+    def __exit__(self, *exc):
+        if self.ctx is not None:
+            self.ctx.__exit__(*exc)
+        return False
+
+
+def _check_out(out: torch.Tensor, shape, dtype, device, what: str = "out") -> None:
+    """A caller-supplied output must match exactly: the C ABI takes no output
+    size, so a wrong shape, dtype or layout would be an out-of-bounds write."""
+    if (tuple(out.shape) != tuple(shape) or out.dtype != dtype or not out.is_contiguous() or not out.is_cuda
+            or out.device != torch.device(device)):
+        raise ValueError("%s must be a contiguous %s tensor of shape %s on %s, got %s %s%s on %s"
+                         % (what, dtype, tuple(shape), device, out.dtype, tuple(out.shape),
+                            "" if out.is_contiguous() else " (non-contiguous)", out.device))
+
+
 def _workspace(nbytes: int, device, workspace: Optional[torch.Tensor]) -> torch.Tensor:
     if workspace is not None:
+        if not workspace.is_cuda or not workspace.is_contiguous() or workspace.device != torch.device(device):
+            raise ValueError("workspace must be a contiguous tensor on %s" % (device,))
         if workspace.numel() * workspace.element_size() < nbytes:
             raise ValueError("workspace too small: %d < %d bytes" % (workspace.numel() * workspace.element_size(), nbytes))
         return workspace
@@ -68,6 +100,10 @@ def _workspace(nbytes: int, device, workspace: Optional[torch.Tensor]) -> torch.
 
 def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _ws_bytes(ws: torch.Tensor) -> int:
+    return ws.numel() * ws.element_size()
 
 
 def drt3d_forward(vol: torch.Tensor, mask: int = DRT3D_ALL, out: Optional[torch.Tensor] = None,
@@ -82,14 +118,13 @@ def drt3d_forward(vol: torch.Tensor, mask: int = DRT3D_ALL, out: Optional[torch.
     else:
         dt, odt = _dtype_code(vol), vol.dtype
     shape = drt3d_out_shape(N, mask)
-    if out is None:
-        out = torch.empty(shape, dtype=odt, device=vol.device)
-    elif tuple(out.shape) != shape or out.dtype != odt or not out.is_contiguous():
-        raise ValueError("out must be a contiguous %s tensor of shape %s" % (odt, shape))
-    need = lib().drt3d_workspace_bytes(N, mask, dt)
-    ws = _workspace(need, vol.device, workspace)
-    check(lib().drt3d_forward(_ptr(vol), _ptr(out), N, mask, dt, _ptr(ws), ws.numel() * ws.element_size(),
-                              _stream(stream)))
+    with _on_stream(stream):
+        if out is None:
+            out = torch.empty(shape, dtype=odt, device=vol.device)
+        else:
+            _check_out(out, shape, odt, vol.device)
+        ws = _workspace(lib().drt3d_workspace_bytes(N, mask, dt), vol.device, workspace)
+        check(lib().drt3d_forward(_ptr(vol), _ptr(out), N, mask, dt, _ptr(ws), _ws_bytes(ws), _stream(stream)))
     return out
 
 
@@ -99,67 +134,87 @@ def djt3d_forward(vol: torch.Tensor, mask: int = DRT3D_ALL, out: Optional[torch.
     N = _cube(vol)
     dt = _dtype_code(vol)
     shape = djt3d_out_shape(N, mask)
-    if out is None:
-        out = torch.empty(shape, dtype=vol.dtype, device=vol.device)
-    elif tuple(out.shape) != shape or out.dtype != vol.dtype or not out.is_contiguous():
-        raise ValueError("out must be a contiguous %s tensor of shape %s" % (vol.dtype, shape))
-    need = lib().djt3d_workspace_bytes(N, mask, dt)
-    ws = _workspace(need, vol.device, workspace)
-    check(lib().djt3d_forward(_ptr(vol), _ptr(out), N, mask, dt, _ptr(ws), ws.numel() * ws.element_size(),
-                              _stream(stream)))
+    with _on_stream(stream):
+        if out is None:
+            out = torch.empty(shape, dtype=vol.dtype, device=vol.device)
+        else:
+            _check_out(out, shape, vol.dtype, vol.device)
+        ws = _workspace(lib().djt3d_workspace_bytes(N, mask, dt), vol.device, workspace)
+        check(lib().djt3d_forward(_ptr(vol), _ptr(out), N, mask, dt, _ptr(ws), _ws_bytes(ws), _stream(stream)))
     return out
+
+
+def _proj(proj: torch.Tensor, mask: int, kind: str) -> int:
+    """N of a DRT ('drt') or DJT ('djt') projection in the forward layout of mask."""
+    ndim, shape_of = (4, drt3d_out_shape) if kind == "drt" else (5, djt3d_out_shape)
+    if proj.dim() != ndim or proj.shape[0] != dodecant_count(mask):
+        raise ValueError("proj must be %s for mask %#x, got %s" % (
+            "[popcount][N][N][3N-2]" if kind == "drt" else "[popcount][N][N][2N-1][2N-1]", mask, tuple(proj.shape)))
+    N = int(proj.shape[1])
+    if tuple(proj.shape) != shape_of(N, mask) or not proj.is_cuda or not proj.is_contiguous():
+        raise ValueError("proj must be a contiguous device tensor of shape %s" % (shape_of(N, mask),))
+    return N
 
 
 def drt3d_adjoint(proj: torch.Tensor, mask: int = DRT3D_ALL, out: Optional[torch.Tensor] = None,
                   workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """Backprojection (exact transpose of drt3d_forward): [N][N][N]."""
-    if proj.dim() != 4 or proj.shape[0] != dodecant_count(mask):
-        raise ValueError("proj must be [popcount(mask)][N][N][3N-2]")
-    N = int(proj.shape[1])
-    if tuple(proj.shape) != drt3d_out_shape(N, mask) or not proj.is_cuda or not proj.is_contiguous():
-        raise ValueError("proj must be a contiguous device tensor of shape %s" % (drt3d_out_shape(N, mask),))
+    N = _proj(proj, mask, "drt")
     dt = _dtype_code(proj)
-    if out is None:
-        out = torch.empty((N, N, N), dtype=proj.dtype, device=proj.device)
-    need = lib().drt3d_adjoint_workspace_bytes(N, mask, dt)
-    ws = _workspace(need, proj.device, workspace)
-    check(lib().drt3d_adjoint(_ptr(proj), _ptr(out), N, mask, dt, _ptr(ws), ws.numel() * ws.element_size(),
-                              _stream(stream)))
+    with _on_stream(stream):
+        if out is None:
+            out = torch.empty((N, N, N), dtype=proj.dtype, device=proj.device)
+        else:
+            _check_out(out, (N, N, N), proj.dtype, proj.device)
+        ws = _workspace(lib().drt3d_adjoint_workspace_bytes(N, mask, dt), proj.device, workspace)
+        check(lib().drt3d_adjoint(_ptr(proj), _ptr(out), N, mask, dt, _ptr(ws), _ws_bytes(ws), _stream(stream)))
     return out
 
 
 def djt3d_adjoint(proj: torch.Tensor, mask: int = DRT3D_ALL, out: Optional[torch.Tensor] = None,
                   workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """Exact transpose of djt3d_forward: [N][N][N]."""
-    if proj.dim() != 5 or proj.shape[0] != dodecant_count(mask):
-        raise ValueError("proj must be [popcount(mask)][N][N][2N-1][2N-1]")
-    N = int(proj.shape[1])
-    if tuple(proj.shape) != djt3d_out_shape(N, mask) or not proj.is_cuda or not proj.is_contiguous():
-        raise ValueError("proj must be a contiguous device tensor of shape %s" % (djt3d_out_shape(N, mask),))
+    N = _proj(proj, mask, "djt")
     dt = _dtype_code(proj)
-    if out is None:
-        out = torch.empty((N, N, N), dtype=proj.dtype, device=proj.device)
-    elif tuple(out.shape) != (N, N, N) or out.dtype != proj.dtype or not out.is_contiguous():
-        raise ValueError("out must be a contiguous %s tensor of shape %s" % (proj.dtype, (N, N, N)))
-    need = lib().djt3d_adjoint_workspace_bytes(N, mask, dt)
-    ws = _workspace(need, proj.device, workspace)
-    check(lib().djt3d_adjoint(_ptr(proj), _ptr(out), N, mask, dt, _ptr(ws), ws.numel() * ws.element_size(),
-                              _stream(stream)))
+    with _on_stream(stream):
+        if out is None:
+            out = torch.empty((N, N, N), dtype=proj.dtype, device=proj.device)
+        else:
+            _check_out(out, (N, N, N), proj.dtype, proj.device)
+        ws = _workspace(lib().djt3d_adjoint_workspace_bytes(N, mask, dt), proj.device, workspace)
+        check(lib().djt3d_adjoint(_ptr(proj), _ptr(out), N, mask, dt, _ptr(ws), _ws_bytes(ws), _stream(stream)))
     return out
 
 
-def _batched(fn_name: str, ws_name: str, ins: Sequence[torch.Tensor], outs: Sequence[torch.Tensor],
-             Ns: Sequence[int], mask: int, dt: int, device, workspace, stream):
+def _batched(fn_name: str, ws_name: str, ins: Sequence[torch.Tensor], outs: Optional[Sequence[torch.Tensor]],
+             out_shape, Ns: Sequence[int], mask: int, dt: int, workspace, stream) -> List[torch.Tensor]:
+    """Checks that the inputs share one dtype and device, allocates or checks
+    one output per input (out_shape(N)), then makes the batched call."""
+    dev, tdt = ins[0].device, ins[0].dtype
+    for t in ins:
+        if t.dtype != tdt:
+            raise TypeError("all inputs of a batched call must share one dtype (%s and %s)" % (tdt, t.dtype))
+        if t.device != dev:
+            raise ValueError("all inputs of a batched call must be on one device (%s and %s)" % (dev, t.device))
     count = len(ins)
-    a_in = (ctypes.c_void_p * count)(*[t.data_ptr() for t in ins])
-    a_out = (ctypes.c_void_p * count)(*[t.data_ptr() for t in outs])
-    a_N = (ctypes.c_int * count)(*Ns)
-    need = getattr(lib(), ws_name)(count, a_N, mask, dt)
-    if need == 0:
-        raise ValueError("invalid batched arguments")
-    ws = _workspace(need, device, workspace)
-    check(getattr(lib(), fn_name)(count, a_in, a_out, a_N, mask, dt, _ptr(ws), ws.numel() * ws.element_size(),
-                                  _stream(stream)))
+    with _on_stream(stream):
+        if outs is None:
+            outs = [torch.empty(out_shape(N), dtype=tdt, device=dev) for N in Ns]
+        else:
+            outs = list(outs)
+            if len(outs) != count:
+                raise ValueError("outs holds %d tensors for %d inputs" % (len(outs), count))
+            for i, (o, N) in enumerate(zip(outs, Ns)):
+                _check_out(o, out_shape(N), tdt, dev, "outs[%d]" % i)
+        a_in = (ctypes.c_void_p * count)(*[t.data_ptr() for t in ins])
+        a_out = (ctypes.c_void_p * count)(*[t.data_ptr() for t in outs])
+        a_N = (ctypes.c_int * count)(*Ns)
+        need = getattr(lib(), ws_name)(count, a_N, mask, dt)
+        if need == 0:
+            raise ValueError("invalid batched arguments")
+        ws = _workspace(need, dev, workspace)
+        check(getattr(lib(), fn_name)(count, a_in, a_out, a_N, mask, dt, _ptr(ws), _ws_bytes(ws), _stream(stream)))
+    return outs
 
 
 def drt3d_forward_batched(vols: Sequence[torch.Tensor], mask: int = DRT3D_ALL,
@@ -170,92 +225,59 @@ def drt3d_forward_batched(vols: Sequence[torch.Tensor], mask: int = DRT3D_ALL,
         return []
     Ns = [_cube(v) for v in vols]
     dt = _dtype_code(vols[0])
-    if any(v.dtype != vols[0].dtype for v in vols):
-        raise TypeError("all volumes must share one dtype")
-    if outs is None:
-        outs = [torch.empty(drt3d_out_shape(N, mask), dtype=vols[0].dtype, device=vols[0].device) for N in Ns]
-    _batched("drt3d_forward_batched", "drt3d_forward_batched_workspace_bytes", vols, outs, Ns, mask, dt,
-             vols[0].device, workspace, stream)
-    return list(outs)
+    return _batched("drt3d_forward_batched", "drt3d_forward_batched_workspace_bytes", vols, outs,
+                    lambda N: drt3d_out_shape(N, mask), Ns, mask, dt, workspace, stream)
 
 
 def djt3d_forward_batched(vols: Sequence[torch.Tensor], mask: int = DRT3D_ALL,
                           outs: Optional[Sequence[torch.Tensor]] = None,
                           workspace: Optional[torch.Tensor] = None, stream=None) -> List[torch.Tensor]:
+    """DJT of many cubes (mixed N, same dtype) in one set of persistent launches."""
     if not vols:
         return []
     Ns = [_cube(v) for v in vols]
     dt = _dtype_code(vols[0])
-    if outs is None:
-        outs = [torch.empty(djt3d_out_shape(N, mask), dtype=vols[0].dtype, device=vols[0].device) for N in Ns]
-    _batched("djt3d_forward_batched", "djt3d_forward_batched_workspace_bytes", vols, outs, Ns, mask, dt,
-             vols[0].device, workspace, stream)
-    return list(outs)
+    return _batched("djt3d_forward_batched", "djt3d_forward_batched_workspace_bytes", vols, outs,
+                    lambda N: djt3d_out_shape(N, mask), Ns, mask, dt, workspace, stream)
 
 
 def drt3d_adjoint_batched(projs: Sequence[torch.Tensor], mask: int = DRT3D_ALL,
                           outs: Optional[Sequence[torch.Tensor]] = None,
                           workspace: Optional[torch.Tensor] = None, stream=None) -> List[torch.Tensor]:
+    """DRT adjoints of many projections (mixed N, same dtype)."""
     if not projs:
         return []
-    Ns = []
-    for p in projs:
-        N = int(p.shape[1])
-        if tuple(p.shape) != drt3d_out_shape(N, mask) or not p.is_contiguous() or not p.is_cuda:
-            raise ValueError("each projection must be a contiguous device tensor [popcount][N][N][3N-2]")
-        Ns.append(N)
+    Ns = [_proj(p, mask, "drt") for p in projs]
     dt = _dtype_code(projs[0])
-    if outs is None:
-        outs = [torch.empty((N, N, N), dtype=projs[0].dtype, device=projs[0].device) for N in Ns]
-    _batched("drt3d_adjoint_batched", "drt3d_adjoint_batched_workspace_bytes", projs, outs, Ns, mask, dt,
-             projs[0].device, workspace, stream)
-    return list(outs)
+    return _batched("drt3d_adjoint_batched", "drt3d_adjoint_batched_workspace_bytes", projs, outs,
+                    lambda N: (N, N, N), Ns, mask, dt, workspace, stream)
 
 
 def djt3d_adjoint_batched(projs: Sequence[torch.Tensor], mask: int = DRT3D_ALL,
                           outs: Optional[Sequence[torch.Tensor]] = None,
                           workspace: Optional[torch.Tensor] = None, stream=None) -> List[torch.Tensor]:
+    """DJT adjoints of many projections (mixed N, same dtype)."""
     if not projs:
         return []
-    Ns = []
-    for p in projs:
-        N = int(p.shape[1])
-        if tuple(p.shape) != djt3d_out_shape(N, mask) or not p.is_contiguous() or not p.is_cuda:
-            raise ValueError("each projection must be a contiguous device tensor [popcount][N][N][2N-1][2N-1]")
-        Ns.append(N)
+    Ns = [_proj(p, mask, "djt") for p in projs]
     dt = _dtype_code(projs[0])
-    if outs is None:
-        outs = [torch.empty((N, N, N), dtype=projs[0].dtype, device=projs[0].device) for N in Ns]
-    _batched("djt3d_adjoint_batched", "djt3d_adjoint_batched_workspace_bytes", projs, outs, Ns, mask, dt,
-             projs[0].device, workspace, stream)
-    return list(outs)
+    return _batched("djt3d_adjoint_batched", "djt3d_adjoint_batched_workspace_bytes", projs, outs,
+                    lambda N: (N, N, N), Ns, mask, dt, workspace, stream)
 
 
 def drt3d_merge_net(proj: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """Algorithm 2's merged output: the 12-dodecant DRT rotated and placed in a
     [4N][4N][3N-2] net (the four corner blocks zero)."""
-    if proj.dim() != 4:
-        raise ValueError("proj must be [12][N][N][3N-2]")
-    N = int(proj.shape[1])
-    if tuple(proj.shape) != drt3d_out_shape(N) or not proj.is_cuda or not proj.is_contiguous():
-        raise ValueError("proj must be a contiguous 12-dodecant device tensor of shape %s" % (drt3d_out_shape(N),))
+    N = _proj(proj, DRT3D_ALL, "drt")
     dt = _dtype_code(proj)
     shape = (4 * N, 4 * N, 3 * N - 2)
-    if out is None:
-        out = torch.empty(shape, dtype=proj.dtype, device=proj.device)
-    elif tuple(out.shape) != shape or out.dtype != proj.dtype or not out.is_contiguous():
-        raise ValueError("out must be a contiguous %s tensor of shape %s" % (proj.dtype, shape))
-    check(lib().drt3d_merge_net(_ptr(proj), _ptr(out), N, dt, _stream(stream)))
+    with _on_stream(stream):
+        if out is None:
+            out = torch.empty(shape, dtype=proj.dtype, device=proj.device)
+        else:
+            _check_out(out, shape, proj.dtype, proj.device)
+        check(lib().drt3d_merge_net(_ptr(proj), _ptr(out), N, dt, _stream(stream)))
     return out
-
-
-def _proj_N(proj: torch.Tensor, mask: int) -> int:
-    if proj.dim() != 4:
-        raise ValueError("proj must be [count][N][N][3N-2]")
-    N = int(proj.shape[1])
-    if tuple(proj.shape) != drt3d_out_shape(N, mask) or not proj.is_cuda or not proj.is_contiguous():
-        raise ValueError("proj must be a contiguous device tensor of shape %s" % (drt3d_out_shape(N, mask),))
-    return N
 
 
 def drt3d_detect_planes(proj: torch.Tensor, cos_tol: float = 0.05, rel_threshold: float = 0.5,
@@ -266,15 +288,15 @@ def drt3d_detect_planes(proj: torch.Tensor, cos_tol: float = 0.05, rel_threshold
     then the qualifying planes in ascending order, at most cap of them) and
     count the number found (which may exceed cap). Reads count back, so the
     call waits for the stream."""
-    N = _proj_N(proj, mask)
+    N = _proj(proj, mask, "drt")
     dt = _dtype_code(proj)
-    ws = _workspace(lib().drt3d_detect_planes_workspace_bytes(N, mask, dt), proj.device, workspace)
-    bins = torch.empty(max(1, int(cap)), dtype=torch.int64, device=proj.device)
-    count = torch.empty(1, dtype=torch.int64, device=proj.device)
-    check(lib().drt3d_detect_planes(_ptr(proj), N, mask, dt, float(cos_tol), float(rel_threshold), _ptr(bins),
-                                    bins.numel(), _ptr(count), _ptr(ws), ws.numel() * ws.element_size(),
-                                    _stream(stream)))
-    n = int(count.item())
+    with _on_stream(stream):
+        ws = _workspace(lib().drt3d_detect_planes_workspace_bytes(N, mask, dt), proj.device, workspace)
+        bins = torch.empty(max(1, int(cap)), dtype=torch.int64, device=proj.device)
+        count = torch.empty(1, dtype=torch.int64, device=proj.device)
+        check(lib().drt3d_detect_planes(_ptr(proj), N, mask, dt, float(cos_tol), float(rel_threshold), _ptr(bins),
+                                        bins.numel(), _ptr(count), _ptr(ws), _ws_bytes(ws), _stream(stream)))
+        n = int(count.item())
     return bins[:min(n, bins.numel())], n
 
 
@@ -285,17 +307,20 @@ def drt3d_backproject_bins(bins: torch.Tensor, N: int, mask: int = DRT3D_ALL, dt
     0/1 projection marking the flat indices in bins (int64 device tensor)."""
     if bins.dtype != torch.int64 or not bins.is_cuda or bins.dim() != 1 or not bins.is_contiguous():
         raise ValueError("bins must be a contiguous 1-D int64 device tensor")
+    if dtype not in (torch.int32, torch.float32):
+        raise TypeError("dtype must be torch.int32 or torch.float32")
     dt = DRT3D_F32 if dtype == torch.float32 else DRT3D_I32
-    if out is None:
-        out = torch.empty((N, N, N), dtype=dtype, device=bins.device)
-    elif tuple(out.shape) != (N, N, N) or out.dtype != dtype or not out.is_contiguous():
-        raise ValueError("out must be a contiguous %s tensor of shape %s" % (dtype, (N, N, N)))
-    ws = _workspace(lib().drt3d_backproject_bins_workspace_bytes(N, mask, dt), bins.device, workspace)
-    count = torch.full((1,), bins.numel(), dtype=torch.int64, device=bins.device)
-    if bins.numel() == 0:  # no planes: a valid pointer, nothing read
-        bins = torch.zeros(1, dtype=torch.int64, device=bins.device)
-    check(lib().drt3d_backproject_bins(_ptr(bins), _ptr(count), bins.numel(), _ptr(out), N, mask, dt,
-                                       _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    with _on_stream(stream):
+        if out is None:
+            out = torch.empty((N, N, N), dtype=dtype, device=bins.device)
+        else:
+            _check_out(out, (N, N, N), dtype, bins.device)
+        ws = _workspace(lib().drt3d_backproject_bins_workspace_bytes(N, mask, dt), bins.device, workspace)
+        count = torch.full((1,), bins.numel(), dtype=torch.int64, device=bins.device)
+        if bins.numel() == 0:  # no planes: a valid pointer, nothing read
+            bins = torch.zeros(1, dtype=torch.int64, device=bins.device)
+        check(lib().drt3d_backproject_bins(_ptr(bins), _ptr(count), bins.numel(), _ptr(out), N, mask, dt,
+                                           _ptr(ws), _ws_bytes(ws), _stream(stream)))
     return out
 
 
@@ -309,7 +334,7 @@ def drt3d_plane_normal(k: int, s1: int, s2: int, N: int):
 def _inverse_workspace(N: int, device, workspace):
     need = lib().drt3d_inverse_workspace_bytes(N)
     if need == 0:
-        raise ValueError("the inverse takes N a power of two >= 2, got %d" % N)
+        raise ValueError("the inverse takes N a power of two in [2, 512], got %d" % N)
     return _workspace(need, device, workspace)
 
 
@@ -320,34 +345,35 @@ def drt3d_inverse(proj: torch.Tensor, cycles: int = 10, lams: Optional[Sequence[
 
     lams: the eigenvalues for sizes 2, 4, ..., N (as drt3d_inverse_lambdas
     returns them), or None to let the library compute and cache them."""
-    if proj.dim() != 4 or proj.dtype != torch.float32:
-        raise ValueError("proj must be a float32 [12][N][N][3N-2] tensor")
-    N = int(proj.shape[1])
-    if tuple(proj.shape) != drt3d_out_shape(N) or not proj.is_cuda or not proj.is_contiguous():
-        raise ValueError("proj must be a contiguous device tensor of shape %s" % (drt3d_out_shape(N),))
-    if out is None:
-        out = torch.empty((N, N, N), dtype=torch.float32, device=proj.device)
-    elif tuple(out.shape) != (N, N, N) or out.dtype != torch.float32 or not out.is_contiguous():
-        raise ValueError("out must be a contiguous float32 tensor of shape %s" % ((N, N, N),))
-    ws = _inverse_workspace(N, proj.device, workspace)
+    N = _proj(proj, DRT3D_ALL, "drt")
+    if proj.dtype != torch.float32:
+        raise ValueError("the inverse takes a float32 projection")
     n = N.bit_length() - 1
     arr = None
     if lams is not None:
         if len(lams) != n:
             raise ValueError("lams needs %d values (sizes 2 .. %d)" % (n, N))
         arr = (ctypes.c_double * n)(*[float(v) for v in lams])
-    check(lib().drt3d_inverse(_ptr(proj), _ptr(out), N, int(cycles), arr, _ptr(ws), ws.numel() * ws.element_size(),
-                              _stream(stream)))
+    with _on_stream(stream):
+        if out is None:
+            out = torch.empty((N, N, N), dtype=torch.float32, device=proj.device)
+        else:
+            _check_out(out, (N, N, N), torch.float32, proj.device)
+        ws = _inverse_workspace(N, proj.device, workspace)
+        check(lib().drt3d_inverse(_ptr(proj), _ptr(out), N, int(cycles), arr, _ptr(ws), _ws_bytes(ws),
+                                  _stream(stream)))
     return out
 
 
 def drt3d_inverse_lambdas(N: int, device="cuda", workspace: Optional[torch.Tensor] = None, stream=None) -> List[float]:
     """The smoother's eigenvalues for sizes 2, 4, ..., N (computed once per size)."""
-    ws = _inverse_workspace(N, device, workspace)
     n = N.bit_length() - 1
     arr = (ctypes.c_double * n)()
-    check(lib().drt3d_inverse_lambdas(N, arr, _ptr(ws), ws.numel() * ws.element_size(), _stream(stream)))
+    with _on_stream(stream):
+        ws = _inverse_workspace(N, device, workspace)
+        check(lib().drt3d_inverse_lambdas(N, arr, _ptr(ws), _ws_bytes(ws), _stream(stream)))
     return list(arr)
+
 
 
 def drt3d_autotune(N: int, dtype=torch.float32, device="cuda") -> str:

@@ -868,7 +868,8 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             if (K == 2) return nch <= 6;
             return waves == 8 ? nch <= 3 : (nch != 2 && nch <= 5);
         };
-        fuse_last = runs4 && chunk == nd && g0.Kx == g0.Ky && (g0.Kx == 2 || g0.Kx == 3) && (w0 == 8 || w0 == 16) &&
+        // (its volume and slot byte offsets are 32-bit: N <= 512)
+        fuse_last = N <= 512 && runs4 && chunk == nd && g0.Kx == g0.Ky && (g0.Kx == 2 || g0.Kx == 3) && (w0 == 8 || w0 == 16) &&
                     choose_tiles(g0, 1, t.lds_elems, T0, H0, L0, nt0) && (L0 & 63) == 0 &&
                     fused_fits(g0.Kx, w0, L0 >> 6) && drt_adj_group_kernel(is_float, g0.Kx, L0 >> 6, w0) != nullptr;
         fuse_waves = w0;

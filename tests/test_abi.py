@@ -203,6 +203,34 @@ def test_plan_text_lists_the_launches():
     assert L.drt3d_plan_text(4, 16, 0xFFF, 0, buf, len(buf)) == EINVAL
 
 
+def test_sizes_above_the_limit_are_rejected():
+    """N = 1024 is past the 32-bit byte offsets of the kernels: every query
+    answers 0 and every entry point EINVAL, before any device work, in the
+    single-volume and the batched forms alike."""
+    L = _lib()
+    A = _fake(1 << 20)
+    big = 1 << 40
+    buf = ctypes.create_string_buffer(1 << 12)
+    Ns = (ctypes.c_int * 2)(8, 1024)
+    ptrs = (ctypes.c_void_p * 2)(1 << 20, 1 << 21)
+    for N in (1024, 2048):
+        assert L.drt3d_out_elems(N, 0x001) == 0
+        assert L.drt3d_workspace_bytes(N, 0x001, 0) == 0
+        assert L.drt3d_adjoint_workspace_bytes(N, 0x001, 1) == 0
+        assert L.drt3d_inverse_workspace_bytes(N) == 0
+        assert L.drt3d_net_elems(N) == 0
+        assert L.drt3d_forward(A, A, N, 0x001, 0, A, big, None) == EINVAL
+        assert L.drt3d_adjoint(A, A, N, 0x001, 0, A, big, None) == EINVAL
+        assert L.drt3d_forward(A, A, N, 0x001, 2, A, big, None) == EINVAL
+        for op in (0, 1, 2, 3):
+            assert L.drt3d_plan_text(op, N, 0x001, 0, buf, len(buf)) == EINVAL
+    assert L.drt3d_forward_batched_workspace_bytes(2, Ns, 0x001, 0) == 0
+    assert L.drt3d_adjoint_batched_workspace_bytes(2, Ns, 0x001, 0) == 0
+    assert L.drt3d_forward_batched(2, ptrs, ptrs, Ns, 0x001, 0, A, big, None) == EINVAL
+    assert L.drt3d_adjoint_batched(2, ptrs, ptrs, Ns, 0x001, 0, A, big, None) == EINVAL
+    assert L.drt3d_out_elems(512, 0x001) == 512 * 512 * 1534
+
+
 @pytest.mark.parametrize("kind", [0, 1])
 def test_frame_maps_agree_with_the_oracle(oracle_mod, kind):
     """The library's affine frame maps (offset = base + sx*a + sy*b + sd*c into

@@ -1,16 +1,24 @@
 """Parity at the full sizes of the measured workloads, in the launch
 configuration the benchmark times (default tuning, caller-provided workspace).
 
-The oracle evaluates sampled outputs one by one (its point evaluators follow
-eqs. (9) and (13) directly); properties that hold at any size (per-slope sums,
-support, the adjoint's closed forms and the dot-product identity) cover the
-rest of each output."""
+Element by element: every output of the N = 512 int32 forward against the
+oracle's recursion (Algorithm 1), one layout group of four dodecants at a
+time; two whole dodecants of the N = 128 DJT (Algorithm 3); every output of
+every cube of the 96-cube float32 batch, and the whole forward and backward of
+the 8 x 128^3 float32 differentiable batch, against the FP64 oracle, each with
+its normwise error and max |err| / R(|f|) printed and bounded by 1e-5.
+Sampled outputs through the point evaluators (eqs. (9) and (13) directly) and
+properties that hold at any size (per-slope sums, support, the adjoint's
+closed forms and the dot-product identity) add independent checks."""
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
 import oracle as O
 import workloads
-from tests.gpu_util import FLOAT_TOL, announce, to_dev
+from tests.gpu_util import FLOAT_TOL, announce, float_errors, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -23,6 +31,13 @@ def _api():
 def _ws(nbytes):
     import torch
     return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+
+def _pmap(fn, items, workers=None):
+    """fn over items on host threads (the oracle's C calls release the GIL)."""
+    workers = workers or max(1, min(len(items), 8, os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, items))
 
 
 def _samples(rng, count, hi, edges):
@@ -62,6 +77,21 @@ def test_drt_n512_sampled_outputs(drt512):
         got = out[k][idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
         ref = np.array([O.drt_point(vol, k, s1, s2, dd) for (s1, s2, dd) in pts], dtype=np.int64)
         assert np.array_equal(got.astype(np.int64), ref), "dodecant %d" % k
+
+
+@pytest.mark.parametrize("group", [0, 1, 2])
+def test_drt_n512_every_element(drt512, group):
+    """Every output of the four dodecants of one volume layout group (z-normal
+    k0-k3; y-normal k4, k7, k9, k10; x-normal k5, k6, k8, k11) equals the
+    oracle's recursion, bit for bit."""
+    N, vol, _, out = drt512
+    dods = {0: (0, 1, 2, 3), 1: (4, 7, 9, 10), 2: (5, 6, 8, 11)}[group]
+    announce("fullsize drt N=512 every element, dodecants %s (oracle on the host)" % (dods,))
+    refs = _pmap(lambda k: O.wrap_int32(O.rec_drt(vol, 1 << k)[0]), list(dods), workers=4)
+    for k, ref in zip(dods, refs):
+        got = out[k].cpu().numpy()
+        bad = np.count_nonzero(got != ref)
+        assert bad == 0, "dodecant %d: %d of %d outputs differ" % (k, bad, ref.size)
 
 
 def test_drt_n512_slope_sums_and_support(drt512):
@@ -165,15 +195,110 @@ def test_djt_n128_sampled_sums_and_support():
     torch.cuda.empty_cache()
 
 
-def test_batched_mixed_float_sampled_against_fp64():
-    """The 96-cube mixed batch (float32) through one batched call: sampled
-    outputs of every cube within 1e-5 of the FP64 oracle, relative to R(|f|)."""
+def test_djt_n128_two_dodecants_every_element():
+    """Every output of dodecant 0 (z-normal frame) and dodecant 5 (x-normal
+    frame) of the N = 128 DJT equals the oracle's recursion (Algorithm 3),
+    bit for bit."""
+    import torch
+    from paper_2501_13664_amd._lib import lib
+    api = _api()
+    N = 128
+    vol = workloads.noise_with_segments(N, seed=3)
+    out = torch.empty(api.djt3d_out_shape(N), dtype=torch.int32, device="cuda")
+    ws = _ws(lib().djt3d_workspace_bytes(N, 0xFFF, 0))
+    announce("fullsize djt N=128 every element of dodecants 0 and 5")
+    api.djt3d_forward(to_dev(vol), out=out, workspace=ws)
+    del ws
+    refs = _pmap(lambda k: O.wrap_int32(O.rec_djt(vol, 1 << k)[0]), [0, 5], workers=2)
+    for k, ref in zip((0, 5), refs):
+        got = out[k].cpu().numpy()
+        bad = np.count_nonzero(got != ref)
+        assert bad == 0, "dodecant %d: %d of %d outputs differ" % (k, bad, ref.size)
+    del out
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def mixed_batch_out():
+    """The 96-cube float32 batch through one batched call (the benchmark's
+    launch), outputs kept on the GPU."""
     import torch
     api = _api()
     cubes = workloads.mixed_batch()
     dev = [to_dev(c) for c in cubes]
-    announce("fullsize batched mixed float32")
+    announce("fullsize batched mixed float32 (96 cubes)")
     outs = api.drt3d_forward_batched(dev)
+    torch.cuda.synchronize()
+    yield cubes, outs
+    del outs, dev
+    torch.cuda.empty_cache()
+
+
+def _fp64_drt_errors(cube, got):
+    """(normwise, max |err| / R(|f|)) of a float32 12-dodecant output against
+    the FP64 oracle's recursion; R(|f|) is the FP64 transform of |f|."""
+    c64 = cube.astype(np.float64)
+    y64 = O.rec_drt(c64)
+    r_abs = O.rec_drt(np.abs(c64))
+    return float_errors(got, y64, r_abs)
+
+
+@pytest.mark.parametrize("N", [32, 64, 128, 256])
+def test_batched_mixed_float_every_element_against_fp64(mixed_batch_out, N):
+    """Every output of every cube of size N in the batch, against FP64:
+    normwise relative error and max |err| / R(|f|) both within 1e-5."""
+    cubes, outs = mixed_batch_out
+    idx = [i for i, c in enumerate(cubes) if c.shape[0] == N]
+    announce("fullsize batched float32 N=%d: %d cubes against FP64" % (N, len(idx)))
+    errs = _pmap(lambda i: _fp64_drt_errors(cubes[i], outs[i].cpu().numpy()), idx,
+                 workers=2 if N >= 256 else 8)
+    for i, (nw, mx) in zip(idx, errs):
+        print("cube %d (N=%d): normwise %.2e, max|err|/R|f| %.2e" % (i, N, nw, mx))
+    worst_nw = max(e[0] for e in errs)
+    worst_mx = max(e[1] for e in errs)
+    print("N=%d worst: normwise %.2e, max|err|/R|f| %.2e" % (N, worst_nw, worst_mx))
+    assert worst_nw <= FLOAT_TOL and worst_mx <= FLOAT_TOL
+
+
+def test_differentiable_batch_every_element_against_fp64():
+    """The differentiable batch (8 float32 N = 128 cubes, 12 dodecants): the
+    autograd forward y = R f and the backward R^T W (the gradient of sum W*y)
+    in every element against the FP64 oracle (Algorithm 1 and its reverse with
+    eq. (17)), each cube's normwise error and max |err| / R(|f|) (R^T|W| for
+    the backward) within 1e-5."""
+    import torch
+    from paper_2501_13664_amd import autograd
+    api = _api()
+    B, N = 8, 128
+    f = workloads.normal_batch(B, N, seed=5)
+    W = workloads.normal_weights((B,) + api.drt3d_out_shape(N), seed=6)
+    announce("fullsize differentiable batch 8x128 float32: forward and backward")
+    fr = to_dev(f).requires_grad_(True)
+    y = autograd.drt3d(fr)
+    y.backward(to_dev(W))
+    y_h = y.detach().cpu().numpy()
+    g_h = fr.grad.cpu().numpy()
+    del y, fr
+    torch.cuda.empty_cache()
+
+    def errs(b):
+        fwd = _fp64_drt_errors(f[b], y_h[b])
+        w64 = W[b].astype(np.float64)
+        bwd = float_errors(g_h[b], O.rec_adj(w64, N), O.rec_adj(np.abs(w64), N))
+        return fwd, bwd
+
+    res = _pmap(errs, list(range(B)))
+    for b, (fwd, bwd) in enumerate(res):
+        print("cube %d: forward normwise %.2e max %.2e; backward normwise %.2e max %.2e" % ((b,) + fwd + bwd))
+        assert max(fwd) <= FLOAT_TOL and max(bwd) <= FLOAT_TOL, b
+
+
+def test_batched_mixed_float_sampled_against_definition(mixed_batch_out):
+    """Sampled outputs of every cube of the batch against the oracle's point
+    evaluator, which sums eq. (9)'s plane directly (not the recursion):
+    within 1e-5 of FP64, relative to R(|f|)."""
+    import torch
+    cubes, outs = mixed_batch_out
     rng = np.random.default_rng(15)
     worst = 0.0
     for i, (c, o) in enumerate(zip(cubes, outs)):
@@ -280,3 +405,52 @@ def test_inverse_n128_converges_and_is_linear():
     rel = float(torch.linalg.vector_norm(xs - xf - 2 * xg) / torch.linalg.vector_norm(xs))
     print("linearity: %.2e" % rel)
     assert rel < 1e-5
+
+
+def test_planted_digital_planes_n512():
+    """P7 at the benchmark's size and shape: the 1 % cloud with eight planes
+    drawn as eq. (9)'s digital planes (value 16). Each planted bin of the GPU
+    output holds exactly 16 times the plane's voxel count, and every slope's
+    displacements sum to the volume's sum."""
+    import torch
+    from paper_2501_13664_amd._lib import lib
+    from tests import planted as P
+    api = _api()
+    N = 512
+    vol, planes = P.point_cloud_with_digital_planes(N, n_planes=8, seed=21)
+    out = torch.empty(api.drt3d_out_shape(N), dtype=torch.int32, device="cuda")
+    ws = _ws(lib().drt3d_workspace_bytes(N, 0xFFF, 0))
+    announce("fullsize drt N=512 planted digital planes")
+    api.drt3d_forward(to_dev(vol), out=out, workspace=ws)
+    del ws
+    for k, s1, s2, dd, count in planes:
+        assert int(out[k, s1, s2, dd]) == 16 * count, (k, s1, s2, dd, count)
+    total = int(vol.astype(np.int64).sum())
+    for k in sorted({p[0] for p in planes}):
+        assert bool((out[k].sum(dim=-1, dtype=torch.int64) == total).all()), k
+    del out
+    torch.cuda.empty_cache()
+
+
+def test_planted_digital_segments_djt_n128():
+    """P7 for the DJT at the benchmark's size: 64 runs of eq. (13)'s digital
+    lines (+8 over noise in [0, 3]); each planted bin of the GPU output holds at
+    least 8 times the segment's voxel count, and equals the oracle's point
+    evaluator there."""
+    import torch
+    from paper_2501_13664_amd._lib import lib
+    from tests import planted as P
+    api = _api()
+    N = 128
+    vol, segs = P.noise_with_digital_segments(N, n_segments=64, seed=22)
+    out = torch.empty(api.djt3d_out_shape(N), dtype=torch.int32, device="cuda")
+    ws = _ws(lib().djt3d_workspace_bytes(N, 0xFFF, 0))
+    announce("fullsize djt N=128 planted digital segments")
+    api.djt3d_forward(to_dev(vol), out=out, workspace=ws)
+    del ws
+    for k, s1, s2, e1, e2, count in segs:
+        got = int(out[k, s1, s2, e1, e2])
+        assert got >= 8 * count, (k, s1, s2, e1, e2, count)
+        assert got == O.djt_point(vol, k, s1, s2, e1, e2)
+    del out
+    torch.cuda.empty_cache()
