@@ -78,11 +78,19 @@ class _on_stream:
         return False
 
 
+def _resolve(device) -> torch.device:
+    """`device` with its index filled in ("cuda" means the current device)."""
+    d = torch.device(device)
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
 def _check_out(out: torch.Tensor, shape, dtype, device, what: str = "out") -> None:
     """A caller-supplied output must match exactly: the C ABI takes no output
     size, so a wrong shape, dtype or layout would be an out-of-bounds write."""
     if (tuple(out.shape) != tuple(shape) or out.dtype != dtype or not out.is_contiguous() or not out.is_cuda
-            or out.device != torch.device(device)):
+            or out.device != _resolve(device)):
         raise ValueError("%s must be a contiguous %s tensor of shape %s on %s, got %s %s%s on %s"
                          % (what, dtype, tuple(shape), device, out.dtype, tuple(out.shape),
                             "" if out.is_contiguous() else " (non-contiguous)", out.device))
@@ -90,7 +98,7 @@ def _check_out(out: torch.Tensor, shape, dtype, device, what: str = "out") -> No
 
 def _workspace(nbytes: int, device, workspace: Optional[torch.Tensor]) -> torch.Tensor:
     if workspace is not None:
-        if not workspace.is_cuda or not workspace.is_contiguous() or workspace.device != torch.device(device):
+        if not workspace.is_cuda or not workspace.is_contiguous() or workspace.device != _resolve(device):
             raise ValueError("workspace must be a contiguous tensor on %s" % (device,))
         if workspace.numel() * workspace.element_size() < nbytes:
             raise ValueError("workspace too small: %d < %d bytes" % (workspace.numel() * workspace.element_size(), nbytes))

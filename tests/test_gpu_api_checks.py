@@ -70,3 +70,18 @@ def test_a_caller_stream_gives_the_same_results():
     assert torch.equal(out, ref) and torch.equal(back, back_ref)
     assert all(torch.equal(o, ref) for o in outs)
     assert np.array_equal(back.cpu().numpy(), back_ref.cpu().numpy())
+
+
+def test_device_given_without_an_index_accepts_buffers_on_the_current_device():
+    """'cuda' names the current device: a workspace or output allocated on
+    'cuda:0' is accepted when the call names the device as 'cuda'."""
+    import torch
+    api = _api()
+    from paper_2501_13664_amd._lib import lib
+    N = 8
+    announce("api checks: device named without an index")
+    ws = torch.empty(lib().drt3d_inverse_workspace_bytes(N), dtype=torch.uint8, device="cuda:0")
+    lams = api.drt3d_inverse_lambdas(N, device="cuda", workspace=ws)
+    assert len(lams) > 0 and all(np.isfinite(lams))
+    with pytest.raises(ValueError):
+        api.drt3d_inverse_lambdas(N, device="cuda", workspace=torch.empty(16, dtype=torch.uint8))
