@@ -108,6 +108,22 @@ size_t djt3d_adjoint_batched_workspace_bytes(int count, const int* Ns, uint32_t 
 int drt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype,
                   void* workspace, size_t workspace_bytes, void* stream);
 
+/* drt3d_forward for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc. The
+ * call allocates nothing (no hipMalloc or hipFree, no pinned host memory, no
+ * allocating library routine): its workspace is a static device array of
+ * 64 MiB that the library holds on every GPU it runs on until the process
+ * ends, and the launch descriptors reach that array as kernel arguments. The
+ * caller passes the volume and the output as for drt3d_forward (same layouts
+ * and dtypes, bit-identical results).
+ * Limit: drt3d_workspace_bytes(N, mask, dtype) <= 64 MiB, i.e. N <= 64 for all
+ * 12 dodecants; larger requests return DRT3D_EINVAL before any device work.
+ * Every call on one GPU uses that GPU's single array, which keeps the last
+ * call's contents: calls that overlap in time on one GPU (on different streams,
+ * or from several host threads) race on it and give undefined results, so
+ * order them, e.g. on one stream. */
+int drt3d_forward_noalloc(const void* vol, void* out, int N, uint32_t mask, int dtype, void* stream);
+
 /* 3D DJT of lines, Algorithm 3 (stage map eq. (15)), driving axis z', over the
  * dodecants of `mask`. out: djt3d_out_elems(N, mask) elements, overwritten.
  * N <= 256 (DRT3D_EUNSUPPORTED above: the output alone is 48 GiB at N = 256). */

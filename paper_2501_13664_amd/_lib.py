@@ -35,6 +35,7 @@ SIGNATURES = {
     "drt3d_adjoint_batched_workspace_bytes": (_sz, [_int, _ints, _u32, _int]),
     "djt3d_adjoint_batched_workspace_bytes": (_sz, [_int, _ints, _u32, _int]),
     "drt3d_forward": (_int, [_vp, _vp, _int, _u32, _int, _vp, _sz, _vp]),
+    "drt3d_forward_noalloc": (_int, [_vp, _vp, _int, _u32, _int, _vp]),
     "djt3d_forward": (_int, [_vp, _vp, _int, _u32, _int, _vp, _sz, _vp]),
     "drt3d_adjoint": (_int, [_vp, _vp, _int, _u32, _int, _vp, _sz, _vp]),
     "djt3d_adjoint": (_int, [_vp, _vp, _int, _u32, _int, _vp, _sz, _vp]),

@@ -136,6 +136,26 @@ def drt3d_forward(vol: torch.Tensor, mask: int = DRT3D_ALL, out: Optional[torch.
     return out
 
 
+def drt3d_forward_noalloc(vol: torch.Tensor, mask: int = DRT3D_ALL, out: Optional[torch.Tensor] = None,
+                          stream=None) -> torch.Tensor:
+    """drt3d_forward in the library's static scratch: the library call itself
+    allocates no device memory (N <= 64 for all 12 dodecants). Calls that
+    overlap in time on one GPU race on that scratch; order them on one stream."""
+    N = _cube(vol)
+    if vol.dtype == torch.uint8:
+        dt, odt = DRT3D_U8, torch.int32
+    else:
+        dt, odt = _dtype_code(vol), vol.dtype
+    shape = drt3d_out_shape(N, mask)
+    with _on_stream(stream):
+        if out is None:
+            out = torch.empty(shape, dtype=odt, device=vol.device)
+        else:
+            _check_out(out, shape, odt, vol.device)
+        check(lib().drt3d_forward_noalloc(_ptr(vol), _ptr(out), N, mask, dt, _stream(stream)))
+    return out
+
+
 def djt3d_forward(vol: torch.Tensor, mask: int = DRT3D_ALL, out: Optional[torch.Tensor] = None,
                   workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """3D DJT of lines over the dodecants of `mask`: [popcount][N][N][2N-1][2N-1]."""

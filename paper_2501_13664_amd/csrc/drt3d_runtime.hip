@@ -637,12 +637,74 @@ static int grid_for(long long total_wg, const DeviceInfo& di, int persistent)
     return (int)std::max(1LL, std::min(total_wg, cap));
 }
 
-static int run_launches(const Program& p, void* d_area, hipStream_t s, const DeviceInfo& di)
+// ------------------------------------------------------------------ no-allocation forward
+// drt3d_forward_noalloc runs in the file-scope device array `scratch` instead
+// of a caller's workspace. Each GPU holds its own copy from the library's load
+// until the process ends. In host code the array's name is only a host-side
+// stand-in: every kernel argument and copy uses the device address that
+// hipGetSymbolAddress returns on each device (taken once per device, with that
+// device current, and kept in g_scratch_ptr).
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;
+
+static int scratch_ptr(void** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(DRT3D_EHIP, "hipGetSymbolAddress gave no address for the static scratch");
+        it = g_scratch_ptr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return DRT3D_OK;
+}
+
+// Descriptor upload with no staging buffer: the bytes travel as the kernel
+// arguments of a one-block copy kernel, kWordsPerPut words per launch.
+constexpr int kWordsPerPut = 480;
+struct WordPut {
+    uint32_t n;
+    uint32_t w[kWordsPerPut];
+};
+
+__global__ void __launch_bounds__(256) put_words_kernel(WordPut put, uint32_t* __restrict__ dst)
+{
+    for (uint32_t i = threadIdx.x; i < put.n; i += blockDim.x) dst[i] = put.w[i];
+}
+
+static int upload_descs_by_args(const Program& p, void* d_area, hipStream_t s)
+{
+    const size_t bytes = p.desc_bytes();
+    if (!bytes) return DRT3D_OK;
+    std::vector<uint32_t> words((bytes + 3) / 4, 0u);
+    char* h = reinterpret_cast<char*>(words.data());
+    if (!p.drt.empty()) memcpy(h, p.drt.data(), p.drt.size() * sizeof(DrtDesc));
+    if (!p.djt.empty()) memcpy(h + p.drt_bytes(), p.djt.data(), p.djt.size() * sizeof(DjtDesc));
+    if (!p.tr.empty())
+        memcpy(h + p.drt_bytes() + p.djt_bytes(), p.tr.data(), p.tr.size() * sizeof(TransDesc));
+    WordPut put;
+    for (size_t w0 = 0; w0 < words.size(); w0 += kWordsPerPut) {
+        put.n = (uint32_t)std::min<size_t>(kWordsPerPut, words.size() - w0);
+        memcpy(put.w, words.data() + w0, put.n * sizeof(uint32_t));
+        hipLaunchKernelGGL(put_words_kernel, dim3(1), dim3(256), 0, s, put, reinterpret_cast<uint32_t*>(d_area) + w0);
+        HIP_TRY(hipGetLastError());
+    }
+    return DRT3D_OK;
+}
+
+// allow_prof = false: no events are created or recorded (the no-allocation path)
+static int run_launches(const Program& p, void* d_area, hipStream_t s, const DeviceInfo& di, bool allow_prof = true)
 {
     const DrtDesc* d_drt = reinterpret_cast<const DrtDesc*>(d_area);
     const DjtDesc* d_djt = reinterpret_cast<const DjtDesc*>((char*)d_area + p.drt_bytes());
     const TransDesc* d_tr = reinterpret_cast<const TransDesc*>((char*)d_area + p.drt_bytes() + p.djt_bytes());
-    const bool prof = g_prof_on.load() != 0;
+    const bool prof = allow_prof && g_prof_on.load() != 0;
     for (const Launch& L : p.launches) {
         hipEvent_t ea = nullptr, eb = nullptr;
         if (prof) {
@@ -1405,9 +1467,10 @@ size_t djt3d_adjoint_batched_workspace_bytes(int count, const int* Ns, uint32_t 
     return batched_ws(S_DJT, 1, count, Ns, mask, dtype);
 }
 
-// One volume, DRT forward or adjoint.
+// One volume, DRT forward or adjoint. noalloc: the forward in the static
+// scratch (drt3d_forward_noalloc), which must hold the whole workspace.
 static int drt_single(const void* in, void* out, int N, uint32_t mask, int dtype, void* ws, size_t ws_bytes,
-                      void* stream, int adjoint)
+                      void* stream, int adjoint, int noalloc = 0)
 {
     const int narrow = dtype == DRT3D_U8;
     if (narrow && adjoint) return fail(DRT3D_EUNSUPPORTED, "8-bit data is taken by drt3d_forward only");
@@ -1416,6 +1479,15 @@ static int drt_single(const void* in, void* out, int N, uint32_t mask, int dtype
     TRY(check_ptr(in, adjoint ? "proj" : "vol"));
     TRY(check_ptr(out, adjoint ? "vol_out" : "out"));
     const size_t need = adjoint ? drt3d_adjoint_workspace_bytes(N, mask, dtype) : drt3d_workspace_bytes(N, mask, dtype);
+    if (noalloc) {
+        if (need > kNoallocScratchBytes)
+            return fail(DRT3D_EINVAL,
+                        "drt3d_forward_noalloc: N = %d with %d dodecants needs %zu bytes of scratch, more than the "
+                        "static %zu (12 dodecants: N <= 64); use drt3d_forward with a workspace",
+                        N, popcount12(mask), need, kNoallocScratchBytes);
+        TRY(scratch_ptr(&ws));
+        ws_bytes = kNoallocScratchBytes;
+    }
     TRY(check_ws(ws, ws_bytes, need));
     DeviceInfo di;
     TRY(device_info(di));
@@ -1434,6 +1506,10 @@ static int drt_single(const void* in, void* out, int N, uint32_t mask, int dtype
             if (L.kind == S_DRT && L.fast_kx < 0)
                 return fail(DRT3D_EUNSUPPORTED, "8-bit volumes: tuning %s has a pass without a narrow kernel",
                             tuning_to_string(t).c_str());
+    if (noalloc) {
+        TRY(upload_descs_by_args(prog, ws, (hipStream_t)stream));
+        return run_launches(prog, ws, (hipStream_t)stream, di, false);
+    }
     return execute(prog, ws, (hipStream_t)stream, di, 0);
 }
 
@@ -1441,6 +1517,11 @@ int drt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype, v
                   size_t workspace_bytes, void* stream)
 {
     return drt_single(vol, out, N, mask, dtype, workspace, workspace_bytes, stream, 0);
+}
+
+int drt3d_forward_noalloc(const void* vol, void* out, int N, uint32_t mask, int dtype, void* stream)
+{
+    return drt_single(vol, out, N, mask, dtype, nullptr, 0, stream, 0, 1);
 }
 
 int drt3d_adjoint(const void* proj, void* vol_out, int N, uint32_t mask, int dtype, void* workspace,

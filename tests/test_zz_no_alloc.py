@@ -1,0 +1,63 @@
+"""drt3d_forward_noalloc, the forward for callers that cannot allocate: it runs
+in the library's static scratch and must give exactly what drt3d_forward gives
+with a caller workspace, call after call, including a smaller call after a
+larger one (the scratch keeps the previous call's contents)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_util import announce, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _api():
+    from paper_2501_13664_amd import api
+    return api
+
+
+def _noalloc_raw(vol, N, mask, dtype_code, out):
+    """The C entry point itself, through ctypes (null stream: the current one)."""
+    from paper_2501_13664_amd._lib import lib
+    return lib().drt3d_forward_noalloc(ctypes.c_void_p(vol.data_ptr()), ctypes.c_void_p(out.data_ptr()), N, mask,
+                                       dtype_code, None)
+
+
+@pytest.mark.parametrize("first,second", [((64, 0xFFF, "int32"), (16, 0xFFF, "int32")),
+                                          ((32, 0xFFF, "float32"), (8, 0b100100100101, "float32"))])
+def test_noalloc_matches_the_workspace_forward_on_consecutive_calls(first, second):
+    import torch
+    api = _api()
+    for i, (N, mask, kind) in enumerate((first, second)):
+        announce("noalloc forward call %d: N=%d mask=0x%x %s" % (i, N, mask, kind))
+        if kind == "int32":
+            vol = to_dev(workloads.uniform_int_cube(N, 0, 255, seed=40 + i))
+            code = 0
+        else:
+            vol = to_dev(np.random.default_rng(50 + i).standard_normal((N, N, N)).astype(np.float32))
+            code = 1
+        ref = api.drt3d_forward(vol, mask=mask)
+        out = torch.full(api.drt3d_out_shape(N, mask), -7, dtype=vol.dtype, device="cuda")
+        assert _noalloc_raw(vol, N, mask, code, out) == 0
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), "call %d (N=%d) differs from drt3d_forward" % (i, N)
+
+
+def test_noalloc_rejects_sizes_beyond_its_scratch_before_device_work():
+    import torch
+    from paper_2501_13664_amd._lib import lib
+    N = 128
+    announce("noalloc forward: N=128 is rejected")
+    vol = torch.zeros((N, N, N), dtype=torch.int32, device="cuda")
+    out = torch.empty(1, dtype=torch.int32, device="cuda")
+    assert _noalloc_raw(vol, N, 0xFFF, 0, out) == -1
+    assert b"noalloc" in lib().drt3d_last_error()
+    # one dodecant at N = 128 fits (its workspace is under the limit) and matches
+    api = _api()
+    mask = 0x001
+    assert lib().drt3d_workspace_bytes(N, mask, 0) <= 64 << 20
+    vol = to_dev(workloads.uniform_int_cube(N, 0, 255, seed=7))
+    got = api.drt3d_forward_noalloc(vol, mask=mask)
+    assert torch.equal(got, api.drt3d_forward(vol, mask=mask))
