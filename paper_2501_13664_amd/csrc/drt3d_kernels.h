@@ -4,7 +4,7 @@
 // shifts along the displacement axis only, and its x-part (slope s1, block
 // bit v1) and y-part (s2, v2) add independent shifts, so the x- and y-stages
 // of a dodecant commute and can be grouped freely (the 2D transform applied
-// twice, Sec. 6.3). A pass runs the x-stages mx0..mx0+Kx-1 and the y-stages
+// twice, Sec. 6.2). A pass runs the x-stages mx0..mx0+Kx-1 and the y-stages
 // my0..my0+Ky-1 on a group of 2^Kx x 2^Ky columns that exchange data only
 // among themselves (those sharing the low slope bits sx0, sy0 and the block
 // bits above each range). The group's columns, over one displacement tile plus

@@ -264,7 +264,7 @@ def _drt2d(O, img):
 
 @pytest.mark.parametrize("N", [4, 8, 16])
 def test_drt_is_2d_drt_applied_twice(oracle_mod, N):
-    """Sec. 6.3 (Wu and Brady): a dodecant of the 3D DRT equals the 2D DRT of
+    """Sec. 6.2 (Wu and Brady): a dodecant of the 3D DRT equals the 2D DRT of
     eq. (3) applied along x' for every y', then along y' for every s1."""
     O = oracle_mod
     vol = workloads.uniform_int_cube(N, -30, 30, seed=N + 5)
