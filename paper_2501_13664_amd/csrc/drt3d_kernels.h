@@ -737,7 +737,8 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
             dsd = fm.sd;
             dE = N;
         }
-        const int accum = d->dst_mode == 1 && d->accum[slot];
+        // only the adjoint's last pass adds into the volume accumulators
+        const bool accum = MODE == 2 && d->dst_mode == 1 && d->accum[slot];
         const int q0 = adjoint ? 0 : H;
 
         // zero pads
@@ -748,9 +749,11 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
         uint32_t carry[SPW];
 #pragma unroll
         for (int i = 0; i < SPW; ++i) carry[i] = 0u;
+        // x * sd for sd = +-1, without a branch: (x ^ neg) - neg, neg = 0 or -1
+        const int sneg = ssd > 0 ? 0 : -1, dneg = dsd > 0 ? 0 : -1;
 
         // columns run with unit stride, up or down (ssd, dsd = +-1): byte
-        // offsets advance by +-256 per 64-element chunk, no multiplies
+        // offsets advance by +-64 SB per 64-element chunk, no multiplies
         auto issue_loads = [&](int d0) {
 #pragma unroll
             for (int i = 0; i < SPW; ++i) {
@@ -759,13 +762,13 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
                 const int dd0 = adjoint ? d0 : d0 - H - sx0 * px - sy0 * py;
                 const int colo = so + y * sys;
                 const int dl = dd0 + lane;
-                const int ob = SB * colo + (ssd > 0 ? SB * dl : -SB * dl);
+                const int ob = SB * colo + ((SB * dl) ^ sneg) - sneg;
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
                     // lanes outside the column get an offset past the resource:
                     // the hardware returns 0 for them without touching memory
                     const bool in = (unsigned)(dl + 64 * c) < (unsigned)sE;
-                    v[i][c] = bload_n<SB>(rs_src, in ? ob + (ssd > 0 ? 64 * SB * c : -64 * SB * c) : -1);
+                    v[i][c] = bload_n<SB>(rs_src, in ? ob + ((64 * SB * c) ^ sneg) - sneg : -1);
                 }
             }
         };
@@ -788,36 +791,74 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 
             // line-aligned store with carry (see store_tile_aligned)
             const bool last_tile = tile + 1 == ntiles;
+            if constexpr (FINAL) {
+                // The slot's window is read from LDS in one batch (in-slot
+                // indices clamped, so that lanes which store nothing still read
+                // inside the work group's LDS), then the lanes inside the
+                // window and the column store: no store waits on its own read.
 #pragma unroll
-            for (int i = 0; i < SPW; ++i) {
-                const int py = py_of<KX, NW>(wave, i);
-                const int y = adjoint ? py : bitrev(py, KY);
-                const int dd0 = adjoint ? d0 - sx0 * px - sy0 * py : d0;
-                const int colo = do_ + y * dys;
-                const int mis = dsd > 0 ? (colo & (LINE - 1)) : ((colo + 1) & (LINE - 1));
-                auto line_floor = [&](int x) {
-                    return dsd > 0 ? x - ((mis + x) & (LINE - 1)) : x - ((x - mis) & (LINE - 1));
-                };
-                const int fbeg = dd0 <= 0 ? dd0 : line_floor(dd0);
-                const int fend = last_tile ? dd0 + T_ : line_floor(dd0 + T_);
-                const T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + q0 - dd0;
-                const int cnt = fend - fbeg;
-                const int fl = fbeg + lane;
-                const int ob = DB * colo + (dsd > 0 ? DB * fl : -DB * fl);
+                for (int i = 0; i < SPW; ++i) {
+                    const int py = py_of<KX, NW>(wave, i);
+                    const int colo = do_ + bitrev(py, KY) * dys;
+                    const int mis = dsd > 0 ? (colo & (LINE - 1)) : ((colo + 1) & (LINE - 1));
+                    auto line_floor = [&](int x) {
+                        return dsd > 0 ? x - ((mis + x) & (LINE - 1)) : x - ((x - mis) & (LINE - 1));
+                    };
+                    const int fbeg = d0 <= 0 ? d0 : line_floor(d0);
+                    const int fend = last_tile ? d0 + T_ : line_floor(d0 + T_);
+                    const T* slot_base = lds + slot_offset(wave + i * NW, Lp, pad);
+                    const int rel = q0 - d0;  // in-slot index of displacement dd: rel + dd
+                    const int cnt = fend - fbeg;
+                    const int fl = fbeg + lane;
+                    const int ob = DB * colo + ((DB * fl) ^ dneg) - dneg;
+                    uint32_t val[NCH + 1];
 #pragma unroll
-                for (int c = 0; c < NCH + 1; ++c) {
-                    const int k = 64 * c + lane;
-                    const int dd = fbeg + k;
-                    if (k < cnt && (unsigned)dd < (unsigned)dE) {
-                        T val = dd < dd0 ? from_bits<T>(carry[i]) : live ? sl[dd] : zero_of<T>();
-                        const int off = ob + (dsd > 0 ? 64 * DB * c : -64 * DB * c);
-                        if (accum) val += from_bits<T>(bload(rs_dst, off));
-                        bstore_n<DB>(rs_dst, off, to_bits(val));
+                    for (int c = 0; c < NCH + 1; ++c)
+                        val[c] = live ? to_bits(slot_base[min(max(rel + fl + 64 * c, -pad), L + pad - 1)]) : 0u;
+                    // only the first chunk reaches below d0: those lanes hold the carry
+                    if (fl < d0) val[0] = carry[i];
+                    const uint32_t next_carry =
+                        !last_tile && live ? to_bits(slot_base[min(max(rel + fend + lane, -pad), L + pad - 1)]) : 0u;
+#pragma unroll
+                    for (int c = 0; c < NCH + 1; ++c) {
+                        const int dd = fl + 64 * c;
+                        if (64 * c + lane < cnt && (unsigned)dd < (unsigned)dE)
+                            bstore_n<DB>(rs_dst, ob + ((64 * DB * c) ^ dneg) - dneg, val[c]);
                     }
+                    if (!last_tile) carry[i] = lane < d0 + T_ - fend ? next_carry : 0u;
                 }
-                if (!last_tile) {
-                    const int tail = dd0 + T_ - fend;
-                    carry[i] = lane < tail && live ? to_bits(sl[fend + lane]) : 0u;
+            } else {
+#pragma unroll
+                for (int i = 0; i < SPW; ++i) {
+                    const int py = py_of<KX, NW>(wave, i);
+                    const int y = adjoint ? py : bitrev(py, KY);
+                    const int dd0 = adjoint ? d0 - sx0 * px - sy0 * py : d0;
+                    const int colo = do_ + y * dys;
+                    const int mis = dsd > 0 ? (colo & (LINE - 1)) : ((colo + 1) & (LINE - 1));
+                    auto line_floor = [&](int x) {
+                        return dsd > 0 ? x - ((mis + x) & (LINE - 1)) : x - ((x - mis) & (LINE - 1));
+                    };
+                    const int fbeg = dd0 <= 0 ? dd0 : line_floor(dd0);
+                    const int fend = last_tile ? dd0 + T_ : line_floor(dd0 + T_);
+                    const T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + q0 - dd0;
+                    const int cnt = fend - fbeg;
+                    const int fl = fbeg + lane;
+                    const int ob = DB * colo + (dsd > 0 ? DB * fl : -DB * fl);
+#pragma unroll
+                    for (int c = 0; c < NCH + 1; ++c) {
+                        const int k = 64 * c + lane;
+                        const int dd = fbeg + k;
+                        if (k < cnt && (unsigned)dd < (unsigned)dE) {
+                            T val = dd < dd0 ? from_bits<T>(carry[i]) : live ? sl[dd] : zero_of<T>();
+                            const int off = ob + (dsd > 0 ? 64 * DB * c : -64 * DB * c);
+                            if (accum) val += from_bits<T>(bload(rs_dst, off));
+                            bstore_n<DB>(rs_dst, off, to_bits(val));
+                        }
+                    }
+                    if (!last_tile) {
+                        const int tail = dd0 + T_ - fend;
+                        carry[i] = lane < tail && live ? to_bits(sl[fend + lane]) : 0u;
+                    }
                 }
             }
             if (live) __syncthreads();
