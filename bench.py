@@ -313,7 +313,7 @@ def adjoint_rate(api, torch, proj, N, reps=3):
     return {"workload": "drt3d_adjoint N=%d int32, 12 dodecants, of the forward's projections" % N,
             "ms": ms, "updates": U, "updates_per_s": U / (ms / 1e3),
             "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS},
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": dbytes / dn},
             "kernels": {k: {"ms_total": v[0], "launches": v[1], "alg_GBps": v[2] / (v[0] / 1e3) / 1e9}
                         for k, v in recs.items()}}
 
@@ -480,6 +480,34 @@ def copy_calibration(torch):
                       "launches": 5}), flush=True)
 
 
+def stream_ceiling(api, torch, read_bytes, write_bytes, src, dst, reps=5):
+    """The reference stream (drt3d_stream_probe) with a kernel's algorithmic
+    read and write bytes: GB/s of the median of `reps` timed runs, the ceiling
+    HBM allows for that mix of reads and writes."""
+    read_bytes = int(read_bytes) // 16 * 16
+    write_bytes = int(write_bytes) // 16 * 16
+    api.stream_probe(src, read_bytes, dst, write_bytes)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        api.stream_probe(src, read_bytes, dst, write_bytes)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = sorted(times)[len(times) // 2]
+    return {"GBps": (read_bytes + write_bytes) / (ms / 1e3) / 1e9, "ms": ms,
+            "read_GB": read_bytes / 1e9, "write_GB": write_bytes / 1e9}
+
+
+def attach_ceiling(roof, ceil):
+    """Adds the same-mix stream ceiling to a roofline record."""
+    roof["ceiling"] = {"GBps": ceil["GBps"], "frac_of_ceiling": roof["achieved"] / ceil["GBps"],
+                       "reference": "drt3d_stream_probe moving the kernel's algorithmic bytes "
+                                    "(%.2f GB read, %.2f GB written) in %.3f ms"
+                                    % (ceil["read_GB"], ceil["write_GB"], ceil["ms"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -574,6 +602,14 @@ def main():
         line["narrow_u8"] = narrow_rate(api, torch, vol_np, out)
     if not args.no_planes:
         line["plane_detection"] = planes_rate(api, torch, out)
+    # the same-mix ceilings (they overwrite out and ws, which are done)
+    out_bytes = 12 * 4 * N * N * (3 * N - 2)
+    fwd_last = recs[dom][2] / recs[dom][1]
+    attach_ceiling(line["roofline"], stream_ceiling(api, torch, fwd_last - out_bytes, out_bytes, ws, out))
+    if "adjoint" in line:
+        adj = line["adjoint"]
+        attach_ceiling(adj["roofline"],
+                       stream_ceiling(api, torch, out_bytes, adj["roofline"]["bytes_per_launch"] - out_bytes, out, ws))
     del ws
     torch.cuda.empty_cache()
     float_checks = []

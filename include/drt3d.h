@@ -277,6 +277,15 @@ int drt3d_profile_reset(void);
 int drt3d_pass_times(char* names /* cap x 32 chars */, double* ms, long long* launches,
                      double* bytes, int cap);
 
+/* ---- reference stream -------------------------------------------------------- */
+/* Not part of any transform: the practical HBM ceiling a pass is measured
+ * against. Reads read_bytes of src and writes write_bytes of dst (device
+ * buffers, 16-byte aligned, byte counts multiples of 16 in [16, 32 GiB]),
+ * interleaved in proportion, 16 bytes per lane, with the non-temporal store
+ * policy of the DRT passes and no arithmetic. Asynchronous on `stream`; time it
+ * with events. DRT3D_EINVAL for bad sizes or pointers. */
+int drt3d_stream_probe(const void* src, size_t read_bytes, void* dst, size_t write_bytes, void* stream);
+
 /* ---- introspection (host only, no GPU work) --------------------------------- */
 /* Frame view of dodecant k (0..11) at size N as an affine element offset
  * out = {base, sx, sy, sd, group}:

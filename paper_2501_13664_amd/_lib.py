@@ -61,6 +61,7 @@ SIGNATURES = {
     "drt3d_profile_reset": (_int, []),
     "drt3d_pass_times": (_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double), _int]),
+    "drt3d_stream_probe": (_int, [_vp, _sz, _vp, _sz, _vp]),
     "drt3d_frame_map": (_int, [_int, _int, _int, _ints]),
     "drt3d_plan_text": (_int, [_int, _int, _u32, _int, ctypes.c_char_p, _sz]),
 }

@@ -427,6 +427,15 @@ def drt3d_set_tuning(N: int, text: str, dtype=torch.float32) -> None:
     check(lib().drt3d_set_tuning(N, dt, text.encode()))
 
 
+def stream_probe(src: torch.Tensor, read_bytes: int, dst: torch.Tensor, write_bytes: int, stream=None) -> None:
+    """The reference stream (drt3d_stream_probe): reads read_bytes of src and
+    writes write_bytes of dst, the HBM ceiling for that mix of reads and writes."""
+    for t, nb, what in ((src, read_bytes, "src"), (dst, write_bytes, "dst")):
+        if not t.is_cuda or not t.is_contiguous() or t.numel() * t.element_size() < nb:
+            raise ValueError("%s must be a contiguous device tensor of at least %d bytes" % (what, nb))
+    check(lib().drt3d_stream_probe(_ptr(src), int(read_bytes), _ptr(dst), int(write_bytes), _stream(stream)))
+
+
 class profile:
     """Context manager collecting per-kernel HIP-event times of library launches.
 

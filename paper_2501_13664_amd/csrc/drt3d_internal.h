@@ -139,6 +139,9 @@ hipError_t launch_transpose_u8(const TransDesc* d_descs, int ndesc, long long to
 const void* drt_adj_group_kernel_3_3(int is_float, int nch, int waves);
 const void* drt_adj_group_kernel_2_2(int is_float, int nch, int waves);
 const void* drt_adj_group_kernel(int is_float, int K, int nch, int waves);
+// reference stream: read read_bytes of src, write write_bytes of dst (16-byte multiples)
+hipError_t launch_stream_probe(const void* src, size_t read_bytes, void* dst, size_t write_bytes, int cus,
+                               hipStream_t s);
 hipError_t launch_drt_adj_group(int is_float, int K, int nch, int waves, const DrtDesc* d_descs, int ndesc,
                                 long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
 

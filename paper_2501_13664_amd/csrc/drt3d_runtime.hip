@@ -2217,6 +2217,23 @@ int drt3d_autotune(int N, int dtype, const void* vol, void* out, void* workspace
     return DRT3D_OK;
 }
 
+// ------------------------------------------------------------------ reference stream
+int drt3d_stream_probe(const void* src, size_t read_bytes, void* dst, size_t write_bytes, void* stream)
+{
+    TRY(check_ptr(src, "src"));
+    TRY(check_ptr(dst, "dst"));
+    const size_t cap = (size_t)32 << 30;
+    if (read_bytes < 16 || write_bytes < 16 || read_bytes % 16 || write_bytes % 16 || read_bytes > cap ||
+        write_bytes > cap)
+        return fail(DRT3D_EINVAL, "stream probe: byte counts must be multiples of 16 in [16, 32 GiB], got %zu and %zu",
+                    read_bytes, write_bytes);
+    DeviceInfo di;
+    TRY(device_info(di));
+    const hipError_t e = launch_stream_probe(src, read_bytes, dst, write_bytes, di.cus, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(DRT3D_EHIP, "launch of the stream probe failed: %s", hipGetErrorString(e));
+    return DRT3D_OK;
+}
+
 // ------------------------------------------------------------------ profiling ABI
 int drt3d_profile_enable(int on)
 {

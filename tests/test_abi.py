@@ -305,3 +305,11 @@ def test_plane_detection_argument_checks():
     for fn, code, word in cases:
         assert fn() == code
         assert word in L.drt3d_last_error().decode()
+
+
+def test_stream_probe_rejects_bad_sizes_before_device_work():
+    L = _lib()
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20)  # never dereferenced: rejected first
+    for rb, wb in ((0, 16), (16, 0), (17, 16), (16, 24), (64 << 30, 16)):
+        assert L.drt3d_stream_probe(a, rb, b, wb, None) == EINVAL
+    assert L.drt3d_stream_probe(None, 16, b, 16, None) == EINVAL
