@@ -49,6 +49,7 @@ template <typename T>
 __device__ __forceinline__ T zero_of() { return T(0); }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <typename T> struct Vec4;
 template <> struct Vec4<uint32_t> { using type = u32x4; };
@@ -747,8 +748,9 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 
         uint32_t v[SPW][NCH];
         uint32_t carry[SPW];
+        uint32_t carry2[SPW];  // the last pass's pair stores carry pairs: the second element
 #pragma unroll
-        for (int i = 0; i < SPW; ++i) carry[i] = 0u;
+        for (int i = 0; i < SPW; ++i) carry[i] = carry2[i] = 0u;
         // x * sd for sd = +-1, without a branch: (x ^ neg) - neg, neg = 0 or -1
         const int sneg = ssd > 0 ? 0 : -1, dneg = dsd > 0 ? 0 : -1;
 
@@ -791,7 +793,48 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 
             // line-aligned store with carry (see store_tile_aligned)
             const bool last_tile = tile + 1 == ntiles;
-            if constexpr (FINAL) {
+            if constexpr (FINAL && DB == 4 && NW == 8) {
+                // Lanes store pairs of elements (8 bytes): every window edge
+                // (line boundaries, column ends, d0 and T are even: 3N - 2, the
+                // tile widths L - H and the halos 2^KX + 2^KY - 2 all are) falls
+                // between pairs, so a pair is stored whole or not at all. The
+                // slot's window is read from LDS in one batch (indices clamped,
+                // so lanes that store nothing still read inside the work
+                // group's LDS), then the pairs inside the window store. (With
+                // sixteen wavefronts the pairs would not fit 64 registers.)
+                constexpr int NP = (NCH + 2) / 2;  // 128-element store chunks
+#pragma unroll
+                for (int i = 0; i < SPW; ++i) {
+                    const int py = py_of<KX, NW>(wave, i);
+                    const int colo = do_ + bitrev(py, KY) * dys;  // even; the output columns run upwards
+                    const int fbeg = d0 <= 0 ? d0 : d0 - ((colo + d0) & (LINE - 1));
+                    const int fend = last_tile ? d0 + T_ : d0 + T_ - ((colo + d0 + T_) & (LINE - 1));
+                    const T* slot_base = lds + slot_offset(wave + i * NW, Lp, pad);
+                    const int rel = q0 - d0;  // in-slot index of displacement dd: rel + dd (even)
+                    const int fl = fbeg + 2 * lane;
+                    u32x2 val[NP];
+#pragma unroll
+                    for (int c = 0; c < NP; ++c) {
+                        const int q = min(max(rel + fl + 128 * c, -pad), L + pad - 2);
+                        val[c] = live ? *reinterpret_cast<const u32x2*>(slot_base + q) : u32x2{0u, 0u};
+                    }
+                    // only the first chunk reaches below d0: those lanes hold the carry
+                    if (fl < d0) val[0] = u32x2{carry[i], carry2[i]};
+                    u32x2 next_carry = {0u, 0u};
+                    if (!last_tile && live)
+                        next_carry = *reinterpret_cast<const u32x2*>(
+                            slot_base + min(max(rel + fend + 2 * lane, -pad), L + pad - 2));
+#pragma unroll
+                    for (int c = 0; c < NP; ++c) {
+                        const int dd = fl + 128 * c;
+                        if (dd < fend && (unsigned)dd < (unsigned)dE)
+                            __builtin_amdgcn_raw_buffer_store_b64(val[c], rs_dst, 4 * (colo + dd), 0, kStorePolicy);
+                    }
+                    const bool keep = !last_tile && 2 * lane < d0 + T_ - fend;
+                    carry[i] = keep ? next_carry.x : 0u;
+                    carry2[i] = keep ? next_carry.y : 0u;
+                }
+            } else if constexpr (FINAL) {
                 // The slot's window is read from LDS in one batch (in-slot
                 // indices clamped, so that lanes which store nothing still read
                 // inside the work group's LDS), then the lanes inside the
