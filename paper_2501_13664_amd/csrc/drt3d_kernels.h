@@ -793,20 +793,21 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 
             // line-aligned store with carry (see store_tile_aligned)
             const bool last_tile = tile + 1 == ntiles;
-            if constexpr (FINAL && DB == 4 && NW == 8) {
-                // Lanes store pairs of elements (8 bytes): every window edge
-                // (line boundaries, column ends, d0 and T are even: 3N - 2, the
-                // tile widths L - H and the halos 2^KX + 2^KY - 2 all are) falls
-                // between pairs, so a pair is stored whole or not at all. The
-                // slot's window is read from LDS in one batch (indices clamped,
-                // so lanes that store nothing still read inside the work
-                // group's LDS), then the pairs inside the window store. (With
-                // sixteen wavefronts the pairs would not fit 64 registers.)
+            if constexpr (MODE != 2 && DB == 4 && NW == 8) {
+                // Forward passes: lanes store pairs of elements (8 bytes). Every
+                // window edge (line boundaries, column ends, d0 and T) is even,
+                // since 3N - 2, the stage extents and pitches, the tile widths
+                // L - H and the halos 2^KX + 2^KY - 2 all are, so a pair is
+                // stored whole or not at all. The slot's window is read from
+                // LDS in one batch (indices clamped, so lanes that store nothing
+                // still read inside the work group's LDS), then the pairs inside
+                // the window store. (With sixteen wavefronts the pairs would not
+                // fit 64 registers.)
                 constexpr int NP = (NCH + 2) / 2;  // 128-element store chunks
 #pragma unroll
                 for (int i = 0; i < SPW; ++i) {
                     const int py = py_of<KX, NW>(wave, i);
-                    const int colo = do_ + bitrev(py, KY) * dys;  // even; the output columns run upwards
+                    const int colo = do_ + bitrev(py, KY) * dys;  // even; forward outputs run upwards
                     const int fbeg = d0 <= 0 ? d0 : d0 - ((colo + d0) & (LINE - 1));
                     const int fend = last_tile ? d0 + T_ : d0 + T_ - ((colo + d0 + T_) & (LINE - 1));
                     const T* slot_base = lds + slot_offset(wave + i * NW, Lp, pad);
