@@ -1283,17 +1283,23 @@ static int djt_steps(std::vector<Step>& steps, int N, uint32_t mask, int chunked
 }
 
 // ------------------------------------------------------------------ graphs
+// At most kMaxGraphs executable graphs are kept; the least recently used one
+// is destroyed to make room, once its last replay has finished.
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // recorded after each replay
+    unsigned long long last_use = 0;
 };
+static constexpr size_t kMaxGraphs = 32;
 static std::mutex g_graph_mu;
 static std::map<std::string, GraphEntry> g_graphs;
+static unsigned long long g_graph_clock = 0;
 
-static std::string program_signature(const Program& p, void* d_area)
+static std::string program_signature(const Program& p, void* d_area, int dev)
 {
     std::string sig;
     char buf[128];
-    snprintf(buf, sizeof buf, "%p|%d|", d_area, p.is_float);
+    snprintf(buf, sizeof buf, "%d|%p|%d|", dev, d_area, p.is_float);
     sig += buf;
     for (const Launch& L : p.launches) {
         snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%d:%zu:%d.%d.%d:%d%d%d%d:%d%d%d;", L.kind, L.first, L.ndesc,
@@ -1313,10 +1319,21 @@ static std::string program_signature(const Program& p, void* d_area)
 // descriptor area, so a graph stays valid while the workspace does.
 static int run_graph(const Program& p, void* d_area, hipStream_t s, const DeviceInfo& di)
 {
-    const std::string sig = program_signature(p, d_area);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const std::string sig = program_signature(p, d_area, dev);
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(sig);
     if (it == g_graphs.end()) {
+        if (g_graphs.size() >= kMaxGraphs) {
+            auto lru = g_graphs.begin();
+            for (auto q = g_graphs.begin(); q != g_graphs.end(); ++q)
+                if (q->second.last_use < lru->second.last_use) lru = q;
+            if (lru->second.done) HIP_TRY(hipEventSynchronize(lru->second.done));
+            HIP_TRY(hipGraphExecDestroy(lru->second.exec));
+            if (lru->second.done) (void)hipEventDestroy(lru->second.done);
+            g_graphs.erase(lru);
+        }
         hipStream_t cs = s;
         bool own = false;
         if (s == nullptr) {  // the legacy default stream cannot be captured
@@ -1334,9 +1351,15 @@ static int run_graph(const Program& p, void* d_area, hipStream_t s, const Device
         const hipError_t e2 = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e2 != hipSuccess) return fail(DRT3D_EHIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e2));
+        if (hipEventCreateWithFlags(&ge.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGraphExecDestroy(ge.exec);
+            return fail(DRT3D_EHIP, "hipEventCreateWithFlags failed");
+        }
         it = g_graphs.emplace(sig, ge).first;
     }
+    it->second.last_use = ++g_graph_clock;
     HIP_TRY(hipGraphLaunch(it->second.exec, s));
+    HIP_TRY(hipEventRecord(it->second.done, s));
     return DRT3D_OK;
 }
 

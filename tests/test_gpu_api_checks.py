@@ -1,6 +1,8 @@
 """The Python binding rejects caller buffers that do not match before any
 library call (the C ABI takes no output sizes, so a mismatch would be an
 out-of-bounds device write), and runs correctly on a caller's own stream."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -85,3 +87,25 @@ def test_device_given_without_an_index_accepts_buffers_on_the_current_device():
     assert len(lams) > 0 and all(np.isfinite(lams))
     with pytest.raises(ValueError):
         api.drt3d_inverse_lambdas(N, device="cuda", workspace=torch.empty(16, dtype=torch.uint8))
+
+
+def test_batched_calls_with_many_workspaces_stay_correct():
+    """Each fresh workspace address is a new replay graph; past the cache's
+    bound the least recently used ones are destroyed and the calls go on
+    giving the single-volume results."""
+    import torch
+    api = _api()
+    from paper_2501_13664_amd._lib import lib
+    announce("api checks: 40 batched calls on 40 workspaces")
+    vols = [to_dev(workloads.uniform_int_cube(n, 0, 99, seed=60 + n)) for n in (8, 16)]
+    refs = [api.drt3d_forward(v) for v in vols]
+    need = lib().drt3d_forward_batched_workspace_bytes(2, (ctypes.c_int * 2)(8, 16), 0xFFF, 0)
+    keep = []
+    for i in range(40):
+        ws = torch.empty(need + 256 * (i + 1), dtype=torch.uint8, device="cuda")[256 * (i + 1):]
+        keep.append(ws)  # distinct addresses
+        outs = api.drt3d_forward_batched(vols, workspace=ws)
+        if i % 13 == 0 or i == 39:
+            torch.cuda.synchronize()
+            assert all(torch.equal(o, r) for o, r in zip(outs, refs)), "call %d" % i
+    torch.cuda.synchronize()
