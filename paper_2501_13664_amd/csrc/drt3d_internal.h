@@ -133,7 +133,9 @@ int drt_fast_available(int kx, int ky, int nch, int waves, int mode = 0, int sb 
 hipError_t launch_drt_fast(int is_float, int kx, int ky, int nch, int mode, int waves, const DrtDesc* d_descs,
                            int ndesc, long long total_wg, int grid, size_t lds_bytes, hipStream_t s, int sb = 4,
                            int db = 4);
-hipError_t launch_transpose_u8(const TransDesc* d_descs, int ndesc, long long total_wg, hipStream_t s);
+// wide: 128 x 128 tiles moved as 4-byte words (every R, C and base a multiple
+// of 4, no accumulation); else the element-wise 64 x 64 kernel
+hipError_t launch_transpose_u8(const TransDesc* d_descs, int ndesc, long long total_wg, int wide, hipStream_t s);
 // The adjoint's last pass fused over layout groups (square K.K passes, K = 2
 // or 3; eight wavefronts, or sixteen for 3.3).
 const void* drt_adj_group_kernel_3_3(int is_float, int nch, int waves);

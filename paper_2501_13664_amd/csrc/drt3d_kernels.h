@@ -793,8 +793,9 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 
             // line-aligned store with carry (see store_tile_aligned)
             const bool last_tile = tile + 1 == ntiles;
-            if constexpr (MODE != 2 && DB == 4 && NW == 8) {
-                // Forward passes: lanes store pairs of elements (8 bytes). Every
+            if constexpr (MODE != 2 && (DB == 4 || DB == 2) && NW == 8) {
+                // Forward passes: lanes store pairs of elements (8 bytes, or two
+                // 16-bit halves of one word in narrow storage). Every
                 // window edge (line boundaries, column ends, d0 and T) is even,
                 // since 3N - 2, the stage extents and pitches, the tile widths
                 // L - H and the halos 2^KX + 2^KY - 2 all are, so a pair is
@@ -828,8 +829,13 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 #pragma unroll
                     for (int c = 0; c < NP; ++c) {
                         const int dd = fl + 128 * c;
-                        if (dd < fend && (unsigned)dd < (unsigned)dE)
-                            __builtin_amdgcn_raw_buffer_store_b64(val[c], rs_dst, 4 * (colo + dd), 0, kStorePolicy);
+                        if (dd < fend && (unsigned)dd < (unsigned)dE) {
+                            if constexpr (DB == 4)
+                                __builtin_amdgcn_raw_buffer_store_b64(val[c], rs_dst, 4 * (colo + dd), 0, kStorePolicy);
+                            else
+                                __builtin_amdgcn_raw_buffer_store_b32((val[c].x & 0xffffu) | (val[c].y << 16), rs_dst,
+                                                                      2 * (colo + dd), 0, kStorePolicy);
+                        }
                     }
                     const bool keep = !last_tile && 2 * lane < d0 + T_ - fend;
                     carry[i] = keep ? next_carry.x : 0u;

@@ -417,6 +417,7 @@ struct Launch {
     int fast_mode = 0;                              // ... 0 forward, 1 forward last pass, 2 adjoint
     int fast_sb = 4, fast_db = 4;                   // ... storage bytes of its source and destination
     int tr_bytes = 4;                               // transposes: element bytes
+    int tr_wide = 0;                                // transposes: 128-byte tiles of 8-bit elements
     int adj_group = 0;                              // DRT: drt_adj_last_group (fast_nch chunks)
     int djt_k = 0, djt_ncc = 0, djt_nco = 0;        // DJT: stages fused per pass, LDS/output row chunks
     int djt_adj = 0;                                // DJT: the pass's transpose
@@ -502,6 +503,14 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
             // steps of one key write different volumes: one launch is race-free
             L.tr_bytes = s0->t_bytes;
             L.first = (int)prog.tr.size();
+            // 8-bit copies move 4-byte words when every row and base is whole words
+            L.tr_wide = L.tr_bytes == 1;
+            for (size_t q = i; q < j; ++q) {
+                const Step* t = order[q];
+                if (t->t_add || t->t_R % 4 || t->t_C % 4 || ((uintptr_t)t->t_in & 3) || ((uintptr_t)t->t_out & 3))
+                    L.tr_wide = 0;
+            }
+            const int te = L.tr_wide ? 128 : 64;  // tile edge in elements
             long long wg = 0;
             for (size_t q = i; q < j; ++q) {
                 const Step* t = order[q];
@@ -509,8 +518,8 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
                 d.wg_begin = wg;
                 d.in = t->t_in; d.out = t->t_out; d.R = t->t_R; d.C = t->t_C;
                 d.batches = t->t_batches; d.add = t->t_add;
-                d.tiles_r = (t->t_R + 63) / 64;
-                d.tiles_c = (t->t_C + 63) / 64;
+                d.tiles_r = (t->t_R + te - 1) / te;
+                d.tiles_c = (t->t_C + te - 1) / te;
                 wg += (long long)d.tiles_r * d.tiles_c * d.batches;
                 prog.tr.push_back(d);
                 L.bytes += t->bytes;
@@ -739,7 +748,7 @@ static int run_launches(const Program& p, void* d_area, hipStream_t s, const Dev
         } else if (L.kind == S_SUM) {
             e = launch_sum_parts(p.is_float, L.sum_in, L.sum_parts, L.sum_out, L.sum_n, L.sum_accum, s);
         } else if (L.tr_bytes == 1) {
-            e = launch_transpose_u8(d_tr + L.first, L.ndesc, L.total_wg, s);
+            e = launch_transpose_u8(d_tr + L.first, L.ndesc, L.total_wg, L.tr_wide, s);
         } else {
             e = launch_transpose(p.is_float, d_tr + L.first, L.ndesc, L.total_wg, s);
         }
@@ -1304,7 +1313,7 @@ static std::string program_signature(const Program& p, void* d_area, int dev)
     for (const Launch& L : p.launches) {
         snprintf(buf, sizeof buf, "%d:%d:%d:%lld:%d:%d:%zu:%d.%d.%d:%d%d%d%d:%d%d%d;", L.kind, L.first, L.ndesc,
                  L.total_wg, L.persistent, L.block, L.lds, L.fast_kx, L.fast_ky, L.fast_nch + 8 * L.fast_mode, L.djt_k,
-                 L.djt_ncc, L.djt_nco, L.djt_adj, L.fast_sb, L.fast_db, L.tr_bytes + 8 * L.adj_group);
+                 L.djt_ncc, L.djt_nco, L.djt_adj, L.fast_sb, L.fast_db, L.tr_bytes + 8 * L.adj_group + 16 * L.tr_wide);
         sig += buf;
         if (L.kind == S_SUM) {
             snprintf(buf, sizeof buf, "%p>%p:%d:%d:%lld;", L.sum_in, L.sum_out, L.sum_parts, L.sum_accum, L.sum_n);

@@ -60,3 +60,18 @@ def test_u8_forward_n512_benchmark_cube():
     assert torch.equal(got, ref)
     del ref, got
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("offset", [0, 16, 48])
+def test_u8_forward_from_an_offset_view(offset):
+    """A volume that starts inside a larger buffer (on a 16-byte boundary, as
+    the library requires) equals the int32 forward."""
+    import torch
+    api = _api()
+    N = 64
+    vol = np.random.default_rng(90 + offset).integers(0, 256, size=(N, N, N))
+    buf = torch.zeros(N ** 3 + offset, dtype=torch.uint8, device="cuda")
+    buf[offset:] = to_dev(vol.astype(np.uint8).reshape(-1))
+    v8 = buf[offset:].view(N, N, N)
+    announce("u8 forward N=%d from a view at byte offset %d" % (N, offset))
+    assert torch.equal(api.drt3d_forward(v8), api.drt3d_forward(to_dev(vol.astype(np.int32))))
