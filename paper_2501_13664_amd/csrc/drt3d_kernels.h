@@ -643,11 +643,18 @@ __device__ __forceinline__ int py_of(int wave, int i) { return (wave >> KX) + i 
 // narrow storage of 8-bit volumes: 1 for the volume, 2 for the first stage
 // buffer, whose partial sums of at most 2^(KX+KY) <= 256 voxels of 0..255 fit
 // 16 bits). Arithmetic stays 32-bit.
+// The first pass of an 8-bit volume (SB = 1) packs two column groups into
+// the 16-bit halves of each LDS word: every partial sum stays below 2^16, so
+// one 32-bit add adds both halves with no carry between them, and one pass of
+// stages serves two groups. The groups share every shift (the first pass has
+// no skew), and the second group is the first one's neighbour.
 template <typename T, int KX, int KY, int NCH, int MODE, int NW, int SB = 4, int DB = 4>
-__global__ void __launch_bounds__(64 * NW, NW == 16 ? 8 : 6)
+__global__ void __launch_bounds__(64 * NW, NW == 16 ? 8 : SB == 1 && DB == 2 ? 4 : 6)
 drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 {
     static_assert((SB == 4 && DB == 4) || (MODE != 2 && sizeof(T) == 4), "narrow storage: forward passes only");
+    constexpr int PK = SB == 1 && DB == 2 ? 1 : 0;  // column groups packed per work item: 2^PK
+    static_assert(!PK || (MODE == 0 && NW == 8), "packed groups: the 8-bit first pass");
     constexpr int LINE = 128 / DB;  // destination elements per 128-byte line
     constexpr bool FINAL = MODE == 1;
     constexpr int adjoint = MODE == 2 ? 1 : 0;
@@ -665,25 +672,32 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
         const int local = (int)(wg - d->wg_begin);
         const int n = d->n, N = d->N, mx0 = d->mx0, my0 = d->my0;
         const int lg_groups = (n - KX) + (n - KY);
-        int gidx = local & ((1 << lg_groups) - 1);
-        int slot = local >> lg_groups;
+        int gidx = local & ((1 << (lg_groups - PK)) - 1);
+        int slot = local >> (lg_groups - PK);
+        int gidx2 = 2 * gidx + 1;  // packed: the second group, the next along y
+        if (PK) gidx = 2 * gidx;
         if (KX == KY && d->xcd_run > 0) {
             // runs of xcd_run slots; inside a run, work group w takes block
             // (w / (8 run)) * 8 + w % 8 of slot (w / 8) % run, in the layout's
             // own block coordinates, then maps it into the slot's frame
-            const int rl = d->xcd_run, ng = 1 << lg_groups;
+            // (packed: block pairs along the layout's second index)
+            const int rl = d->xcd_run, ng = (1 << lg_groups) >> PK;
             const int run = local / (rl * ng), rem = local - run * rl * ng;
             const int hi = rem / (8 * rl), lo = rem - hi * 8 * rl;
             slot = run * rl + lo / 8;
             const int b = hi * 8 + (lo & 7);
-            const int G = N >> KX;
-            const int b1 = b / G, b2 = b - b1 * G;
+            const int G = N >> KX, GP = G >> PK;
+            const int b1 = b / GP, b2 = (b - b1 * GP) << PK;
             const FrameMap f = d->fm[slot];
             // x' runs along the layout's first index (stride N^2) or its second
             const bool along_first = f.sx == N * N || f.sx == -N * N;
-            const int bx = along_first ? (f.sx > 0 ? b1 : G - 1 - b1) : (f.sx > 0 ? b2 : G - 1 - b2);
-            const int by = along_first ? (f.sy > 0 ? b2 : G - 1 - b2) : (f.sy > 0 ? b1 : G - 1 - b1);
-            gidx = (bx << (n - KY)) | by;
+            auto frame_gidx = [&](int c1, int c2) {
+                const int bx = along_first ? (f.sx > 0 ? c1 : G - 1 - c1) : (f.sx > 0 ? c2 : G - 1 - c2);
+                const int by = along_first ? (f.sy > 0 ? c2 : G - 1 - c2) : (f.sy > 0 ? c1 : G - 1 - c1);
+                return (bx << (n - KY)) | by;
+            };
+            gidx = frame_gidx(b1, b2);
+            if (PK) gidx2 = frame_gidx(b1, b2 + 1);
         }
         const int T_ = d->T, H = d->H, Lp = d->Lp, pad = Lp - L;
         const int gy = gidx & ((1 << (n - KY)) - 1), gx = gidx >> (n - KY);
@@ -738,6 +752,16 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
             dsd = fm.sd;
             dE = N;
         }
+        // packed: the second group's source and destination columns sit a
+        // fixed offset from the first's (a first pass: block columns are
+        // c1 = px + (gx << KX), c2 = py + (gy << KY))
+        int so2 = 0, do2 = 0;
+        if constexpr (PK) {
+            const int gy2 = gidx2 & ((1 << (n - KY)) - 1), gx2 = gidx2 >> (n - KY);
+            const int dc1 = (gx2 - gx) << KX, dc2 = (gy2 - gy) << KY;
+            so2 = fm.sx * dc1 + fm.sy * dc2;        // volume (src_mode 1), bytes
+            do2 = (dc1 * N + dc2) * d->P_out;       // stage buffer (dst_mode 0), elements
+        }
         // only the adjoint's last pass adds into the volume accumulators
         const bool accum = MODE == 2 && d->dst_mode == 1 && d->accum[slot];
         const int q0 = adjoint ? 0 : H;
@@ -747,6 +771,7 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
             if (lane < pad) lds[p * Lp + lane] = zero_of<T>();
 
         uint32_t v[SPW][NCH];
+        uint32_t v2[PK ? SPW : 1][PK ? NCH : 1];  // packed: the second group's elements
         uint32_t carry[SPW];
         uint32_t carry2[SPW];  // the last pass's pair stores carry pairs: the second element
 #pragma unroll
@@ -771,6 +796,7 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
                     // the hardware returns 0 for them without touching memory
                     const bool in = (unsigned)(dl + 64 * c) < (unsigned)sE;
                     v[i][c] = bload_n<SB>(rs_src, in ? ob + ((64 * SB * c) ^ sneg) - sneg : -1);
+                    if constexpr (PK) v2[i][c] = bload_n<SB>(rs_src, in ? so2 + ob + ((64 * SB * c) ^ sneg) - sneg : -1);
                 }
             }
         };
@@ -784,7 +810,10 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
                 for (int i = 0; i < SPW; ++i) {
                     T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + lane;
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) sl[64 * c] = from_bits<T>(v[i][c]);
+                    for (int c = 0; c < NCH; ++c) {
+                        if constexpr (PK) sl[64 * c] = from_bits<T>(v[i][c] | (v2[i][c] << 16));
+                        else sl[64 * c] = from_bits<T>(v[i][c]);
+                    }
                 }
                 __syncthreads();
                 if (tile + 1 < nlive) issue_loads(d0 + T_);
@@ -835,6 +864,9 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
                             else
                                 __builtin_amdgcn_raw_buffer_store_b32((val[c].x & 0xffffu) | (val[c].y << 16), rs_dst,
                                                                       2 * (colo + dd), 0, kStorePolicy);
+                            if constexpr (PK)  // the second group: the high halves
+                                __builtin_amdgcn_raw_buffer_store_b32((val[c].x >> 16) | (val[c].y & 0xffff0000u), rs_dst,
+                                                                      2 * (colo + do2 + dd), 0, kStorePolicy);
                         }
                     }
                     const bool keep = !last_tile && 2 * lane < d0 + T_ - fend;

@@ -544,8 +544,10 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
             if (s->kind == S_DRT) {
                 for (DrtDesc d : s->drt) {
                     d.wg_begin = wg;
-                    // a fused adjoint item covers a group's four dodecants
-                    wg += (long long)(d.fused_group ? d.nslots / 4 : d.nslots) * d.groups_x * d.groups_y;
+                    // a fused adjoint item covers a group's four dodecants; an
+                    // 8-bit first pass packs two column groups per item
+                    wg += ((long long)(d.fused_group ? d.nslots / 4 : d.nslots) * d.groups_x * d.groups_y) >>
+                          (d.sb == 1 && d.db == 2 ? 1 : 0);
                     prog.drt.push_back(d);
                 }
             } else {
@@ -1015,7 +1017,8 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             if (first && !adjoint) {
                 d.src_mode = 1;
                 for (int i = 0; i < 3; ++i) d.vsrc[i] = V[i];
-                if (runs4 && ns % 4 == 0 && g.Kx == g.Ky && ((N >> g.Kx) * (N >> g.Ky)) % 8 == 0) d.xcd_run = 4;
+                const int items = ((N >> g.Kx) * (N >> g.Ky)) >> (d.sb == 1 && d.db == 2 ? 1 : 0);  // per slot
+                if (runs4 && ns % 4 == 0 && g.Kx == g.Ky && items % 8 == 0) d.xcd_run = 4;
             } else if (first) {
                 d.src = io.in;
                 d.src_slot_stride = slot_out;
