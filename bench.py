@@ -216,6 +216,20 @@ def _best_ms(torch, fn, reps):
     return best * 1e3
 
 
+def call_roofline(api, torch, fn, ms):
+    """HBM roofline of a whole call: the algorithmic bytes of every library
+    launch it makes (one profiled run) over the call's best wall time."""
+    with api.profile() as prof:
+        fn()
+        torch.cuda.synchronize()
+    nbytes = sum(v[2] for v in prof.records.values())
+    kernel_ms = sum(v[0] for v in prof.records.values())
+    achieved = nbytes / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "bytes_per_call": nbytes, "kernel_ms": kernel_ms,
+            "launches": sum(v[1] for v in prof.records.values())}
+
+
 def batched_speedup(api, torch, reps=5):
     """96 float32 cubes of mixed N (48 x 32^3, 32 x 64^3, 12 x 128^3, 4 x 256^3):
     one batched call vs per-volume calls on the same stream."""
@@ -240,6 +254,7 @@ def batched_speedup(api, torch, reps=5):
                        "12 dodecants",
            "per_volume_ms": pv, "batched_ms": bt, "speedup": pv / bt, "bit_identical": same,
            "updates": U, "batched_updates_per_s": U / (bt / 1e3),
+           "roofline": call_roofline(api, torch, batched, bt),
            "fp64_error_sample": "every output of all 48 N=32 and 32 N=64 cubes, of the first two N=128 cubes "
                                 "and of the first N=256 cube"}
     # the batched call's results, for the FP64 comparison in the cpu_baseline leg
@@ -285,6 +300,7 @@ def differentiable_speedup(api, torch, reps=5):
     leg = {"workload": "8 float32 N(0,1) cubes N=128 (seed 5), 12 dodecants, grad_out N(0,1) (seed 6)",
            "per_volume_ms": pv, "autograd_ms": ad, "speedup": pv / ad, "bit_identical": same,
            "updates": U, "autograd_updates_per_s": U / (ad / 1e3),
+           "roofline": call_roofline(api, torch, differentiable, ad),
            "fp64_error_sample": "every output of cubes 0 and 1: the forward R f and the gradient R^T g"}
     f_np = workloads.normal_batch(B, N, seed=5)
     g_np = workloads.normal_weights((B,) + api.drt3d_out_shape(N), seed=6)
