@@ -19,7 +19,7 @@ __all__ = [
     "drt3d_inverse", "drt3d_inverse_lambdas", "drt3d_merge_net",
     "drt3d_detect_planes", "drt3d_backproject_bins", "drt3d_plane_normal",
     "drt3d_out_shape", "djt3d_out_shape", "drt3d_autotune", "drt3d_tuning_string",
-    "drt3d_set_tuning", "profile", "dodecant_count",
+    "drt3d_set_tuning", "profile", "dodecant_count", "drt3d_forward_noalloc", "stream_probe",
 ]
 
 
