@@ -286,6 +286,30 @@ int drt3d_pass_times(char* names /* cap x 32 chars */, double* ms, long long* la
  * with events. DRT3D_EINVAL for bad sizes or pointers. */
 int drt3d_stream_probe(const void* src, size_t read_bytes, void* dst, size_t write_bytes, void* stream);
 
+/* ---- plans ------------------------------------------------------------------ */
+/* A plan fixes the shape of one of the four transforms (op as for
+ * drt3d_plan_text: 0 drt3d_forward, 1 drt3d_adjoint, 2 djt3d_forward,
+ * 3 djt3d_adjoint) for size N, dodecant mask and dtype (DRT3D_U8: op 0 only,
+ * N >= 32), and for the DRT the tuning of size class N in force when it is
+ * created (the pass grouping of Algorithm 1's stages, tile width, LDS budget,
+ * wavefronts), so that later drt3d_autotune or drt3d_set_tuning calls leave its
+ * launches unchanged. A plan is a host object: creating, querying and
+ * destroying it does no GPU work, and one plan may run on any device, from
+ * any thread, with any buffers. Arguments are checked as by the op's own call;
+ * a bad one returns DRT3D_EINVAL and leaves *plan NULL. The caller owns the plan
+ * and releases it with drt3d_plan_destroy (NULL is accepted there). */
+typedef struct drt3d_plan_s* drt3d_plan;
+int drt3d_plan_create(drt3d_plan* plan, int op, int N, uint32_t mask, int dtype);
+/* Workspace bytes the plan's execution needs (0 for a NULL plan). */
+size_t drt3d_plan_workspace_bytes(drt3d_plan plan);
+/* Runs the planned transform: in and out as for the op's own call (volume or
+ * projections, in that call's layout and dtype), the workspace at least
+ * drt3d_plan_workspace_bytes(plan) bytes, asynchronous on `stream`. Results
+ * equal the op's own call under the plan's tuning (bit for bit). */
+int drt3d_plan_execute(drt3d_plan plan, const void* in, void* out, void* workspace, size_t workspace_bytes,
+                       void* stream);
+int drt3d_plan_destroy(drt3d_plan plan);
+
 /* ---- introspection (host only, no GPU work) --------------------------------- */
 /* Frame view of dodecant k (0..11) at size N as an affine element offset
  * out = {base, sx, sy, sd, group}:

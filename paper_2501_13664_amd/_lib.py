@@ -63,6 +63,10 @@ SIGNATURES = {
                                 ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double), _int]),
     "drt3d_stream_probe": (_int, [_vp, _sz, _vp, _sz, _vp]),
     "drt3d_frame_map": (_int, [_int, _int, _int, _ints]),
+    "drt3d_plan_create": (_int, [_ptrs, _int, _int, _u32, _int]),
+    "drt3d_plan_workspace_bytes": (_sz, [_vp]),
+    "drt3d_plan_execute": (_int, [_vp, _vp, _vp, _vp, _sz, _vp]),
+    "drt3d_plan_destroy": (_int, [_vp]),
     "drt3d_plan_text": (_int, [_int, _int, _u32, _int, ctypes.c_char_p, _sz]),
 }
 

@@ -19,7 +19,7 @@ __all__ = [
     "drt3d_inverse", "drt3d_inverse_lambdas", "drt3d_merge_net",
     "drt3d_detect_planes", "drt3d_backproject_bins", "drt3d_plane_normal",
     "drt3d_out_shape", "djt3d_out_shape", "drt3d_autotune", "drt3d_tuning_string",
-    "drt3d_set_tuning", "profile", "dodecant_count", "drt3d_forward_noalloc", "stream_probe",
+    "drt3d_set_tuning", "profile", "dodecant_count", "drt3d_forward_noalloc", "stream_probe", "Plan",
 ]
 
 
@@ -434,6 +434,73 @@ def stream_probe(src: torch.Tensor, read_bytes: int, dst: torch.Tensor, write_by
         if not t.is_cuda or not t.is_contiguous() or t.numel() * t.element_size() < nb:
             raise ValueError("%s must be a contiguous device tensor of at least %d bytes" % (what, nb))
     check(lib().drt3d_stream_probe(_ptr(src), int(read_bytes), _ptr(dst), int(write_bytes), _stream(stream)))
+
+
+class Plan:
+    """A fixed transform (drt3d_plan_create): op "drt_forward", "drt_adjoint",
+    "djt_forward" or "djt_adjoint" for size N, mask and dtype (torch.int32,
+    torch.float32, or torch.uint8 for "drt_forward"), keeping the DRT tuning in
+    force when it is made. Calling it runs that transform on `inp` (the op's own
+    input layout); results equal the op's own call under that tuning."""
+
+    OPS = {"drt_forward": 0, "drt_adjoint": 1, "djt_forward": 2, "djt_adjoint": 3}
+    _CODES = {torch.int32: DRT3D_I32, torch.float32: DRT3D_F32, torch.uint8: DRT3D_U8}
+
+    def __init__(self, op: str, N: int, mask: int = DRT3D_ALL, dtype=torch.int32):
+        self._h = None
+        if op not in self.OPS:
+            raise ValueError("op must be one of %s, got %r" % (sorted(self.OPS), op))
+        if dtype not in self._CODES:
+            raise TypeError("plans take int32, float32 or uint8, got %s" % (dtype,))
+        self.op, self.N, self.mask, self.dtype = op, int(N), int(mask), dtype
+        h = ctypes.c_void_p()
+        check(lib().drt3d_plan_create(ctypes.byref(h), self.OPS[op], self.N, self.mask, self._CODES[dtype]))
+        self._h = h
+        self.workspace_bytes = int(lib().drt3d_plan_workspace_bytes(h))
+
+    def shapes(self):
+        """(input shape, output shape)."""
+        vol = (self.N, self.N, self.N)
+        proj = (drt3d_out_shape if self.op.startswith("drt") else djt3d_out_shape)(self.N, self.mask)
+        return (vol, proj) if self.op.endswith("forward") else (proj, vol)
+
+    def __call__(self, inp: torch.Tensor, out: Optional[torch.Tensor] = None,
+                 workspace: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if self._h is None:
+            raise ValueError("the plan is closed")
+        in_shape, out_shape = self.shapes()
+        if (tuple(inp.shape) != in_shape or inp.dtype != self.dtype or not inp.is_cuda
+                or not inp.is_contiguous()):
+            raise ValueError("input must be a contiguous %s device tensor of shape %s, got %s %s"
+                             % (self.dtype, in_shape, inp.dtype, tuple(inp.shape)))
+        odt = torch.int32 if self.dtype == torch.uint8 else self.dtype
+        with _on_stream(stream):
+            if out is None:
+                out = torch.empty(out_shape, dtype=odt, device=inp.device)
+            else:
+                _check_out(out, out_shape, odt, inp.device)
+            ws = _workspace(self.workspace_bytes, inp.device, workspace)
+            check(lib().drt3d_plan_execute(self._h, _ptr(inp), _ptr(out), _ptr(ws), _ws_bytes(ws),
+                                           _stream(stream)))
+        return out
+
+    def close(self) -> None:
+        if self._h is not None:
+            lib().drt3d_plan_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class profile:

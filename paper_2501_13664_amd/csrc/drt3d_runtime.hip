@@ -27,6 +27,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <new>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -1504,8 +1505,9 @@ size_t djt3d_adjoint_batched_workspace_bytes(int count, const int* Ns, uint32_t 
 
 // One volume, DRT forward or adjoint. noalloc: the forward in the static
 // scratch (drt3d_forward_noalloc), which must hold the whole workspace.
+// tune: the tuning to run with (a plan's), else the size class's current one
 static int drt_single(const void* in, void* out, int N, uint32_t mask, int dtype, void* ws, size_t ws_bytes,
-                      void* stream, int adjoint, int noalloc = 0)
+                      void* stream, int adjoint, int noalloc = 0, const Tuning* tune = nullptr)
 {
     const int narrow = dtype == DRT3D_U8;
     if (narrow && adjoint) return fail(DRT3D_EUNSUPPORTED, "8-bit data is taken by drt3d_forward only");
@@ -1527,7 +1529,7 @@ static int drt_single(const void* in, void* out, int N, uint32_t mask, int dtype
     DeviceInfo di;
     TRY(device_info(di));
     const int is_float = dtype == DRT3D_F32;
-    const Tuning t = get_tuning(N, is_float);
+    const Tuning t = tune ? *tune : get_tuning(N, is_float);
     DrtIO io{in, out, (char*)ws + desc_area_bytes(S_DRT, N, mask, 1)};
     std::vector<std::vector<Step>> vols(1);
     TRY(drt_steps(vols[0], N, mask, is_float, adjoint, 1, t, io, narrow));
@@ -2311,6 +2313,62 @@ int drt3d_frame_map(int k, int N, int kind, int out[5])
         return fail(DRT3D_EINVAL, "bad arguments to drt3d_frame_map");
     const FrameMap f = kind == 0 ? drt_frame_map(k, N) : djt_frame_map(k, N);
     out[0] = f.base; out[1] = f.sx; out[2] = f.sy; out[3] = f.sd; out[4] = kind == 0 ? f.group : 0;
+    return DRT3D_OK;
+}
+
+}  // extern "C"
+
+struct drt3d_plan_s {
+    int op, N, dtype;
+    uint32_t mask;
+    Tuning t;  // the DRT's tuning at creation
+};
+
+extern "C" {
+
+int drt3d_plan_create(drt3d_plan* plan, int op, int N, uint32_t mask, int dtype)
+{
+    if (!plan) return fail(DRT3D_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (op < 0 || op > 3) return fail(DRT3D_EINVAL, "op must be 0, 1, 2 or 3");
+    if (dtype == DRT3D_U8) {
+        if (op != 0) return fail(DRT3D_EUNSUPPORTED, "8-bit data is taken by drt3d_forward only");
+        if (N < 32) return fail(DRT3D_EUNSUPPORTED, "8-bit volumes are taken for N >= 32 (got N = %d)", N);
+        TRY(check_common(N, mask, DRT3D_I32));
+    } else {
+        TRY(check_common(N, mask, dtype));
+    }
+    if (op >= 2 && N > 256) return fail(DRT3D_EUNSUPPORTED, "the DJT takes N <= 256 (got N = %d)", N);
+    drt3d_plan_s* p = new (std::nothrow) drt3d_plan_s;
+    if (!p) return fail(DRT3D_ENOMEM, "plan: host allocation failed");
+    p->op = op; p->N = N; p->dtype = dtype; p->mask = mask;
+    p->t = get_tuning(N, dtype == DRT3D_F32);
+    *plan = p;
+    return DRT3D_OK;
+}
+
+size_t drt3d_plan_workspace_bytes(drt3d_plan p)
+{
+    if (!p) return 0;
+    switch (p->op) {
+    case 0: return drt3d_workspace_bytes(p->N, p->mask, p->dtype);
+    case 1: return drt3d_adjoint_workspace_bytes(p->N, p->mask, p->dtype);
+    case 2: return djt3d_workspace_bytes(p->N, p->mask, p->dtype);
+    default: return djt3d_adjoint_workspace_bytes(p->N, p->mask, p->dtype);
+    }
+}
+
+int drt3d_plan_execute(drt3d_plan p, const void* in, void* out, void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!p) return fail(DRT3D_EINVAL, "plan is NULL");
+    if (p->op <= 1)
+        return drt_single(in, out, p->N, p->mask, p->dtype, workspace, workspace_bytes, stream, p->op, 0, &p->t);
+    return djt_single(in, out, p->N, p->mask, p->dtype, workspace, workspace_bytes, stream, p->op == 3);
+}
+
+int drt3d_plan_destroy(drt3d_plan p)
+{
+    delete p;
     return DRT3D_OK;
 }
 

@@ -313,3 +313,37 @@ def test_stream_probe_rejects_bad_sizes_before_device_work():
     for rb, wb in ((0, 16), (16, 0), (17, 16), (16, 24), (64 << 30, 16)):
         assert L.drt3d_stream_probe(a, rb, b, wb, None) == EINVAL
     assert L.drt3d_stream_probe(None, 16, b, 16, None) == EINVAL
+
+
+def test_plan_create_checks_and_workspace_queries():
+    """drt3d_plan_create rejects what the op's own call rejects, leaving the
+    handle NULL; a plan's workspace equals the op's own query; destroy takes
+    NULL; executing a NULL plan or with NULL buffers fails before device work."""
+    L = _lib()
+    EUNSUP = -4
+    h = ctypes.c_void_p(1234)
+    assert L.drt3d_plan_create(None, 0, 32, 0xFFF, 0) == EINVAL
+    for (op, N, mask, dt), want in (((4, 32, 0xFFF, 0), EINVAL), ((-1, 32, 0xFFF, 0), EINVAL),
+                                    ((0, 3, 0xFFF, 0), EINVAL), ((0, 1024, 0xFFF, 0), EINVAL),
+                                    ((1, 32, 0, 0), EINVAL), ((2, 32, 0x1000, 0), EINVAL),
+                                    ((0, 32, 0xFFF, 7), EINVAL), ((1, 64, 0xFFF, 2), EUNSUP),
+                                    ((0, 16, 0xFFF, 2), EUNSUP), ((2, 512, 0x001, 0), EUNSUP)):
+        h.value = 1234
+        assert L.drt3d_plan_create(ctypes.byref(h), op, N, mask, dt) == want, (op, N, mask, dt)
+        assert h.value is None, (op, N, mask, dt)
+    queries = {0: L.drt3d_workspace_bytes, 1: L.drt3d_adjoint_workspace_bytes,
+               2: L.djt3d_workspace_bytes, 3: L.djt3d_adjoint_workspace_bytes}
+    for op in range(4):
+        for N, mask, dt in ((8, 0xFFF, 0), (64, 0x0F0, 1), (32, 0x001, 0)):
+            assert L.drt3d_plan_create(ctypes.byref(h), op, N, mask, dt) == OK
+            assert h.value
+            assert L.drt3d_plan_workspace_bytes(h) == queries[op](N, mask, dt)
+            # NULL buffers are rejected before any device work
+            assert L.drt3d_plan_execute(h, None, None, None, 0, None) == EINVAL
+            assert L.drt3d_plan_destroy(h) == OK
+    assert L.drt3d_plan_create(ctypes.byref(h), 0, 64, 0xFFF, 2) == OK  # uint8 forward
+    assert L.drt3d_plan_workspace_bytes(h) == L.drt3d_workspace_bytes(64, 0xFFF, 2)
+    assert L.drt3d_plan_destroy(h) == OK
+    assert L.drt3d_plan_workspace_bytes(None) == 0
+    assert L.drt3d_plan_execute(None, None, None, None, 0, None) == EINVAL
+    assert L.drt3d_plan_destroy(None) == OK
