@@ -50,8 +50,9 @@ static const void* djt_adj_kernel_k(int ncc)
     case 1: return reinterpret_cast<const void*>(&djt_adj_kernel<T, K, 1>);
     case 2: return reinterpret_cast<const void*>(&djt_adj_kernel<T, K, 2>);
     case 3: return reinterpret_cast<const void*>(&djt_adj_kernel<T, K, 3>);
+    case 4: return reinterpret_cast<const void*>(&djt_adj_kernel<T, K, 4>);
     case 5: return reinterpret_cast<const void*>(&djt_adj_kernel<T, K, 5>);
-    case 9: return reinterpret_cast<const void*>(&djt_adj_kernel<T, K, 9>);
+    case 8: return reinterpret_cast<const void*>(&djt_adj_kernel<T, K, 8>);
     default: return nullptr;
     }
 }
@@ -106,8 +107,9 @@ static int djt_adj_ring_elems(int ncc)
     case 1: return 3 * djt_adj_window<K, 1>();
     case 2: return 3 * djt_adj_window<K, 2>();
     case 3: return 3 * djt_adj_window<K, 3>();
+    case 4: return 3 * djt_adj_window<K, 4>();
     case 5: return 3 * djt_adj_window<K, 5>();
-    case 9: return 3 * djt_adj_window<K, 9>();
+    case 8: return 3 * djt_adj_window<K, 8>();
     default: return 0;
     }
 }
@@ -122,6 +124,13 @@ size_t djt_adj_lds_bytes(int K, int ncc)
 int djt_chunks_for(int cols)
 {
     for (int ncc : kDjtChunkCounts)
+        if (64 * ncc >= cols) return ncc;
+    return 0;
+}
+
+int djt_adj_chunks_for(int cols)
+{
+    for (int ncc : kDjtAdjChunkCounts)
         if (64 * ncc >= cols) return ncc;
     return 0;
 }

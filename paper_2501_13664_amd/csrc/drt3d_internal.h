@@ -104,6 +104,7 @@ int djt_tile_rows(int K);
 int djt_adj_tile_rows();  // forward-output rows per DJT adjoint tile
 size_t djt_adj_lds_bytes(int K, int ncc);  // static LDS of one DJT adjoint work group
 int djt_chunks_for(int cols);
+int djt_adj_chunks_for(int cols);  // the adjoint's: rows of cols = E_out columns
 hipError_t launch_djt_pass(int is_float, int K, int ncc, int nco, const DjtDesc* d_descs, int ndesc,
                            long long total_wg, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_transpose(int is_float, const TransDesc* d_descs, int ndesc, long long total_wg,

@@ -1186,6 +1186,9 @@ constexpr int djt_rows_per_tile(int K) { return 32 >> K; }
 // 64-column chunks of an LDS row (E_out + 2^K - 1 columns), one kernel per
 // count; the largest takes N = 256.
 constexpr int kDjtChunkCounts[] = {1, 2, 3, 5, 9};
+// The adjoint's window rows hold E_out columns (its reads that matter stay
+// below column E_out - 1), one kernel per count; the largest takes N = 256.
+constexpr int kDjtAdjChunkCounts[] = {1, 2, 3, 4, 5, 8};
 
 // NCC: 64-column chunks of an LDS row (E_out + 2^K - 1 columns); NCO: of an
 // output row (E_out columns), NCC or NCC - 1.

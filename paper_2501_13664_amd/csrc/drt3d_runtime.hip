@@ -1228,7 +1228,10 @@ static int djt_steps(std::vector<Step>& steps, int N, uint32_t mask, int chunked
             d.E_in = (int)djt_extent(N, m0);
             d.E_out = (int)djt_extent(N, m0 + K);
             d.P = d.E_out + H;
-            const int ncc = djt_chunks_for(d.P);
+            // the adjoint's window rows hold E_out columns: every read whose
+            // sum is written, at column c + loc(j, B) with c < E_in + s2 j,
+            // stays below E_in + 2^m0 H + H - 1 = E_out - 1
+            const int ncc = adjoint ? djt_adj_chunks_for(d.E_out) : djt_chunks_for(d.P);
             if (ncc == 0) return fail(DRT3D_EUNSUPPORTED, "the DJT is built for N <= 256 (got N = %d)", N);
             d.T1 = adjoint ? djt_adj_tile_rows() : djt_tile_rows(K);
             d.ntiles = (d.E_out + d.T1 - 1) / d.T1;
