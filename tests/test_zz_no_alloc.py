@@ -61,3 +61,18 @@ def test_noalloc_rejects_sizes_beyond_its_scratch_before_device_work():
     vol = to_dev(workloads.uniform_int_cube(N, 0, 255, seed=7))
     got = api.drt3d_forward_noalloc(vol, mask=mask)
     assert torch.equal(got, api.drt3d_forward(vol, mask=mask))
+
+
+def test_noalloc_uint8_volumes():
+    """The 8-bit forward (packed first pass, word-wise frame copies) in the
+    static scratch equals the int32 forward of the same values, twice in a row
+    with a smaller second call."""
+    import torch
+    api = _api()
+    for i, N in enumerate((64, 32)):
+        vol = np.random.default_rng(60 + i).integers(0, 256, size=(N, N, N))
+        announce("noalloc forward uint8 call %d: N=%d" % (i, N))
+        out = torch.full(api.drt3d_out_shape(N), -7, dtype=torch.int32, device="cuda")
+        assert _noalloc_raw(to_dev(vol.astype(np.uint8)), N, 0xFFF, 2, out) == 0
+        torch.cuda.synchronize()
+        assert torch.equal(out, api.drt3d_forward(to_dev(vol.astype(np.int32)))), "call %d (N=%d)" % (i, N)
