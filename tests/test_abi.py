@@ -347,3 +347,19 @@ def test_plan_create_checks_and_workspace_queries():
     assert L.drt3d_plan_workspace_bytes(None) == 0
     assert L.drt3d_plan_execute(None, None, None, None, 0, None) == EINVAL
     assert L.drt3d_plan_destroy(None) == OK
+
+
+def test_djt_builtin_pass_plan(monkeypatch):
+    """The DJT's built-in plan: passes of two stages, and one stage first when
+    log2 N is odd (one launch per pass); DRT3D_DJT_PASSES overrides it, and an
+    override that does not sum to log2 N is ignored."""
+    L = _lib()
+    monkeypatch.delenv("DRT3D_DJT_PASSES", raising=False)
+    buf = ctypes.create_string_buffer(1 << 14)
+    for N in (2, 4, 8, 16, 32, 64, 128, 256):
+        n = N.bit_length() - 1
+        assert L.drt3d_plan_text(2, N, 0x001, 0, buf, len(buf)) == (n + 1) // 2, N
+    monkeypatch.setenv("DRT3D_DJT_PASSES", "3,1,3")
+    assert L.drt3d_plan_text(2, 128, 0x001, 0, buf, len(buf)) == 3
+    monkeypatch.setenv("DRT3D_DJT_PASSES", "3,3")  # sums to 6, not 7
+    assert L.drt3d_plan_text(2, 128, 0x001, 0, buf, len(buf)) == 4
