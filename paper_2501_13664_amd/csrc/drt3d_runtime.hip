@@ -489,6 +489,12 @@ static void build_program(Program& prog, const std::vector<std::vector<Step>>& p
             while (j < order.size() && mergeable[j] && order[j]->key == s0->key && order[j]->kind == s0->kind &&
                    order[j]->shape == s0->shape)
                 ++j;
+        // the forward's volume transposes (keys below kKeyPass) all read
+        // inputs and write distinct copies: one launch takes the run of them
+        if (s0->kind == S_TRANSPOSE && s0->key < kKeyPass)
+            while (j < order.size() && order[j]->kind == S_TRANSPOSE && order[j]->key < kKeyPass &&
+                   order[j]->t_bytes == s0->t_bytes)
+                ++j;
         Launch L;
         L.kind = s0->kind;
         L.name = s0->name;

@@ -182,7 +182,11 @@ def test_plan_text_lists_the_launches():
     n = L.drt3d_plan_text(0, 512, 0xFFF, 0, buf, len(buf))
     text = buf.value.decode()
     assert n == len(text.strip().splitlines())
-    assert text.count("transpose_in") == 2 and "drt_fwd_p" in text
+    # one launch makes both frame copies (y- and x-normal): each reads and
+    # writes the N^3 int32 volume once
+    tr = [l for l in text.splitlines() if l.startswith("transpose_in ")]
+    assert len(tr) == 1 and "drt_fwd_p" in text
+    assert float(tr[0].split("bytes=")[1].split()[0]) == 2 * 2 * 4 * 512 ** 3
     assert all(l.split("kernel=")[1].startswith("fast") for l in text.splitlines() if "kind=0" in l)
     n = L.drt3d_plan_text(1, 64, 0x00F, 1, buf, len(buf))
     text = buf.value.decode()
