@@ -48,6 +48,9 @@ struct DrtDesc {
     // adjoint's last pass, one work item per volume layout group and block:
     // slots 4g .. 4g+3 are group g's four dodecants (drt_adj_last_group)
     int fused_group;
+    // float forward's last pass only: when set, it writes sub - result (the
+    // same layout as the output, e.g. the inverse's residual b - A x)
+    const void* sub;
     int phys[kMaxSlots];   // slot -> slot index inside the source (stage buffer or projections)
     int dphys[kMaxSlots];  // slot -> slot index inside the destination (dst_mode 0)
     int accum[kMaxSlots];  // dst_mode 1: add into the volume (1) or overwrite (0)

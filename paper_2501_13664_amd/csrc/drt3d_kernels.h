@@ -36,6 +36,8 @@
 
 #pragma once
 
+#include <type_traits>
+
 #include "drt3d_internal.h"
 
 namespace drt3d {
@@ -737,9 +739,17 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
             ssd = fm.sd;
             sE = N;
         }
+        // float last pass with `sub`: the stores write sub - result
+        constexpr bool SUBT = FINAL && std::is_same<T, float>::value && DB == 4 && NW == 8;
+        const bool has_sub = SUBT && d->sub != nullptr;
+        __amdgpu_buffer_rsrc_t rs_sub = rs_src;
         if (d->dst_mode == 0) {
             char* base = reinterpret_cast<char*>(d->dst) + (long long)DB * d->dphys[slot] * d->dst_slot_stride;
             rs_dst = make_rsrc_bytes(base, DB * (int)d->dst_slot_stride);
+            if (has_sub)
+                rs_sub = make_rsrc_bytes(reinterpret_cast<const char*>(d->sub) +
+                                             (long long)DB * d->dphys[slot] * d->dst_slot_stride,
+                                         DB * (int)d->dst_slot_stride);
             const int c1 = adjoint ? c1b : c1s, c2 = adjoint ? c2b : c2s;
             do_ = ((c1 << n) + c2) * d->P_out;
             dys = adjoint ? (d->P_out << my0) : d->P_out;
@@ -851,6 +861,23 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
                     }
                     // only the first chunk reaches below d0: those lanes hold the carry
                     if (fl < d0) val[0] = u32x2{carry[i], carry2[i]};
+                    if constexpr (SUBT) {
+                        if (has_sub) {
+                            // the window's pairs of sub, then sub - result (lanes
+                            // outside the window read past the resource: 0)
+                            u32x2 sv[NP];
+#pragma unroll
+                            for (int c = 0; c < NP; ++c) {
+                                const int dd = fl + 128 * c;
+                                sv[c] = __builtin_amdgcn_raw_buffer_load_b64(
+                                    rs_sub, dd < fend && (unsigned)dd < (unsigned)dE ? 4 * (colo + dd) : -1, 0, 0);
+                            }
+#pragma unroll
+                            for (int c = 0; c < NP; ++c)
+                                val[c] = u32x2{to_bits(from_bits<float>(sv[c].x) - from_bits<float>(val[c].x)),
+                                               to_bits(from_bits<float>(sv[c].y) - from_bits<float>(val[c].y))};
+                        }
+                    }
                     u32x2 next_carry = {0u, 0u};
                     if (!last_tile && live)
                         next_carry = *reinterpret_cast<const u32x2*>(

@@ -1834,6 +1834,7 @@ struct InvLayout {
 struct InvProg {
     Program p;
     char* area = nullptr;
+    bool fused_residual = false;  // forward: its last pass writes b - A x itself
 };
 struct InvRun {
     const float* proj;
@@ -1931,6 +1932,16 @@ static int inv_prepare(InvRun& r)
             TRY(drt_steps(vols[0], Nl, DRT3D_ALL, 1, adjoint, 1, t, io));
             ip.p.is_float = 1;
             build_program(ip.p, vols, false);
+            if (!adjoint) {
+                // the residual b - A x is written by the forward's last pass
+                // itself where that pass runs the eight-wavefront specialised
+                // kernel (it reads b where it would otherwise store A x)
+                const Launch& last = ip.p.launches.back();
+                if (last.kind == S_DRT && last.fast_kx >= 0 && last.fast_mode == 1 && last.block == 512) {
+                    for (int q = last.first; q < last.first + last.ndesc; ++q) ip.p.drt[q].sub = inv_b(r, l);
+                    ip.fused_residual = true;
+                }
+            }
             ip.area = r.ws + (adjoint ? r.L.dadj[l] : r.L.dfwd[l]);
             if (ip.p.desc_bytes() > desc_area_bytes(S_DRT, Nl, DRT3D_ALL, 1, adjoint))
                 return fail(DRT3D_EINVAL, "internal: inverse descriptor area too small");
@@ -1946,7 +1957,7 @@ static int inv_residual(InvRun& r, int l)
     const long long Nl = r.N >> l;
     float* T = (float*)(r.ws + r.L.tproj);
     TRY(run_launches(r.fwd[l].p, r.fwd[l].area, r.s, r.di));
-    HIP_TRY(launch_residual(inv_b(r, l), T, T, 12 * Nl * Nl * (3 * Nl - 2), r.s));
+    if (!r.fwd[l].fused_residual) HIP_TRY(launch_residual(inv_b(r, l), T, T, 12 * Nl * Nl * (3 * Nl - 2), r.s));
     return DRT3D_OK;
 }
 
