@@ -791,7 +791,31 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
 
         // columns run with unit stride, up or down (ssd, dsd = +-1): byte
         // offsets advance by +-64 SB per 64-element chunk, no multiplies
+        // packed 8-bit first pass: lanes load 4-byte words (elements dd0 + 4w ...
+        // 4w + 3 of a column; dd0 = d0 - H is a multiple of 4, since the
+        // first pass has no skew and its halo H is rounded up to a multiple
+        // of 4). An ascending column starts on a word (its base has no N - 1
+        // term) and a descending one ends on one (base = 3 mod 4); N is a
+        // multiple of 4, so a word is inside the column whole or not at all.
+        // A descending column's word holds its elements in reverse byte order.
+        constexpr int NWD = (16 * NCH + 63) / 64;  // word loads per slot, group and tile
         auto issue_loads = [&](int d0) {
+            if constexpr (PK) {
+#pragma unroll
+                for (int i = 0; i < SPW; ++i) {
+                    const int colo = so + py_of<KX, NW>(wave, i) * sys;
+#pragma unroll
+                    for (int c = 0; c < NWD; ++c) {
+                        const int w = lane + 64 * c;
+                        const int e = d0 - H + 4 * w;
+                        const bool in = (16 * NCH % 64 == 0 || w < 16 * NCH) && (unsigned)e < (unsigned)sE;
+                        const int off = colo + (e ^ sneg) - sneg + (sneg & -3);
+                        v[i][c] = __builtin_amdgcn_raw_buffer_load_b32(rs_src, in ? off : -1, 0, 0);
+                        v2[i][c] = __builtin_amdgcn_raw_buffer_load_b32(rs_src, in ? so2 + off : -1, 0, 0);
+                    }
+                }
+                return;
+            }
 #pragma unroll
             for (int i = 0; i < SPW; ++i) {
                 const int py = py_of<KX, NW>(wave, i);
@@ -806,7 +830,6 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
                     // the hardware returns 0 for them without touching memory
                     const bool in = (unsigned)(dl + 64 * c) < (unsigned)sE;
                     v[i][c] = bload_n<SB>(rs_src, in ? ob + ((64 * SB * c) ^ sneg) - sneg : -1);
-                    if constexpr (PK) v2[i][c] = bload_n<SB>(rs_src, in ? so2 + ob + ((64 * SB * c) ^ sneg) - sneg : -1);
                 }
             }
         };
@@ -816,13 +839,28 @@ drt_pass_fast(const DrtDesc* __restrict__ descs, int ndesc, long long total_wg)
             const int d0 = tile * T_;
             const bool live = !FINAL || tile < nlive;
             if (live) {
+                if constexpr (PK) {
+                    // the two groups' bytes into the 16-bit halves of 4 LDS words
 #pragma unroll
-                for (int i = 0; i < SPW; ++i) {
-                    T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + lane;
+                    for (int i = 0; i < SPW; ++i) {
+                        T* sl = lds + slot_offset(wave + i * NW, Lp, pad);
 #pragma unroll
-                    for (int c = 0; c < NCH; ++c) {
-                        if constexpr (PK) sl[64 * c] = from_bits<T>(v[i][c] | (v2[i][c] << 16));
-                        else sl[64 * c] = from_bits<T>(v[i][c]);
+                        for (int c = 0; c < NWD; ++c) {
+                            const int w = lane + 64 * c;
+                            const uint32_t xa = sneg ? __builtin_bswap32(v[i][c]) : v[i][c];
+                            const uint32_t xb = sneg ? __builtin_bswap32(v2[i][c]) : v2[i][c];
+                            // bytes k of xa and xb -> (a_k, b_k) 16-bit halves
+                            const u32x4 q = {__builtin_amdgcn_perm(xb, xa, 0x0c040c00u), __builtin_amdgcn_perm(xb, xa, 0x0c050c01u),
+                                             __builtin_amdgcn_perm(xb, xa, 0x0c060c02u), __builtin_amdgcn_perm(xb, xa, 0x0c070c03u)};
+                            if (16 * NCH % 64 == 0 || w < 16 * NCH) *reinterpret_cast<u32x4*>(sl + 4 * w) = q;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < SPW; ++i) {
+                        T* sl = lds + slot_offset(wave + i * NW, Lp, pad) + lane;
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) sl[64 * c] = from_bits<T>(v[i][c]);
                     }
                 }
                 __syncthreads();

@@ -839,13 +839,18 @@ static int fast_max_L(const PassGeom& g)
     return 0;
 }
 
-static bool choose_tiles(const PassGeom& g, int adjoint, int lds_elems, int& T, int& H, int& L, int& ntiles)
+// halign: the halo H rounded up to a multiple of it (every tile then starts
+// on a multiple of it, as the 8-bit first pass's word loads need; a larger
+// halo only computes a few more positions that the tile drops).
+static bool choose_tiles(const PassGeom& g, int adjoint, int lds_elems, int& T, int& H, int& L, int& ntiles,
+                         int halign = 1)
 {
     const int ns = 1 << (g.Kx + g.Ky);
     if (ns > kMaxPassSlots) return false;
     H = ((1 << g.Kx) - 1) + ((1 << g.Ky) - 1);
     const int pad = pass_pad(g);
     if (H / 2 + 2 > pad) return false;
+    H = (H + halign - 1) / halign * halign;
     const int E = adjoint ? g.E_in : g.E_out;  // extent written
     const int skew = adjoint ? ((1 << g.mx0) - 1) * ((1 << g.Kx) - 1) + ((1 << g.my0) - 1) * ((1 << g.Ky) - 1) : 0;
     const int span = E + skew;
@@ -1004,7 +1009,7 @@ static int drt_steps(std::vector<Step>& steps, int N, uint32_t mask, int is_floa
             d.mx0 = g.mx0; d.Kx = g.Kx; d.my0 = g.my0; d.Ky = g.Ky;
             int T, H, L, ntl;
             const int pass_lds = adjoint && !(step == np - 1 && fuse_last) ? adj_lds_of(t) : t.lds_elems;
-            if (!choose_tiles(g, adjoint, pass_lds, T, H, L, ntl))
+            if (!choose_tiles(g, adjoint, pass_lds, T, H, L, ntl, !adjoint && src_bytes(pi) == 1 ? 4 : 1))
                 return fail(DRT3D_EINVAL, "tuning %s cannot fit pass %d in LDS", tuning_to_string(t).c_str(), pi);
             d.T = T; d.H = H; d.L = L; d.Lp = L + pass_pad(g); d.ntiles = ntl;
             d.groups_x = N >> g.Kx;
