@@ -102,7 +102,8 @@ size_t djt3d_adjoint_batched_workspace_bytes(int count, const int* Ns, uint32_t 
  * overwritten. DRT3D_U8 keeps the data narrow in HBM where it fits (Sec. 6
  * points at 8-bit data): the volume and its frame copies at 1 byte, the first
  * pass's partial sums (at most 2^6 voxels of 0..255) at 2 bytes, the rest at 4,
- * with 32-bit arithmetic throughout; it needs a tuning whose passes all have
+ * with 32-bit adds throughout (the first pass adds two column groups at once,
+ * packed in the 16-bit halves of each word); it needs a tuning whose passes all have
  * shape-specialised kernels (the built-in ones for N = 32..512), else
  * DRT3D_EUNSUPPORTED. */
 int drt3d_forward(const void* vol, void* out, int N, uint32_t mask, int dtype,
