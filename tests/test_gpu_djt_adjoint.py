@@ -94,6 +94,28 @@ def test_djt_adjoint_dot_identity_n64():
     assert lhs == rhs
 
 
+def test_djt_adjoint_dot_identity_n256_one_dodecant():
+    """The largest size the DJT takes (its last pass's windows of 8 chunks):
+    <J f, p> = <f, J^T p> for one dodecant at N = 256, sums in int64 over
+    slices (the projections alone are 68 GB)."""
+    import torch
+    api = _api()
+    N, mask = 256, 0x010
+    g = torch.Generator(device="cuda")
+    g.manual_seed(337)
+    f = torch.randint(0, 4, (N, N, N), generator=g, dtype=torch.int32, device="cuda")
+    announce("djt N=256 one dodecant: forward")
+    Jf = api.djt3d_forward(f, mask)
+    p = torch.randint(-8, 9, Jf.shape, generator=g, dtype=torch.int32, device="cuda")
+    announce("djt N=256 one dodecant: adjoint")
+    Jtp = api.djt3d_adjoint(p, mask)
+    lhs = sum(int((Jf[0, i].to(torch.int64) * p[0, i]).sum()) for i in range(N))
+    rhs = int((f.to(torch.int64) * Jtp).sum())
+    del Jf, p, Jtp
+    torch.cuda.empty_cache()
+    assert lhs == rhs
+
+
 def test_djt_adjoint_ones_closed_form_n64():
     """J^T of the all-ones array is popcount(mask) * N^2 at every voxel: each
     voxel lies on one line per dodecant and slope pair."""
