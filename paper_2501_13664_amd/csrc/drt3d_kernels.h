@@ -1430,9 +1430,11 @@ djt_pass_kernel(const DjtDesc* __restrict__ descs, int ndesc, long long total_wg
 // barrier. Each thread accumulates its 2^K x (rows) x (chunks) sums.
 constexpr int kDjtAdjRows = 16;  // forward-output rows e per adjoint tile
 // LDS ring of one adjoint work group: three windows of (T1 + H) rows at a
-// pitch of whole 64-column chunks (every lane of a direct load lands inside
-// its row), plus room past each for the discarded reads of shifted chunks
-// and for the loads of rows a wave does not own
+// pitch of whole 64-column chunks covering E_out (every lane of a direct load
+// lands inside its row; the sums that are written read below column E_out,
+// the others may read into the next row), plus room past each for the
+// discarded reads of shifted chunks and for the loads of rows a wave does
+// not own
 template <int K, int NCC>
 constexpr int djt_adj_window() { return (kDjtAdjRows + (1 << K) - 1) * 64 * NCC + 128; }
 
